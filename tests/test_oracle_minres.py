@@ -1,0 +1,144 @@
+"""Pins of the oracle's preconditioned MINRES (CPU only): Table 1 iteration counts
+and Table 2 errors of Section 3, scipy's independent MINRES, the Krylov minimiser by
+brute force, and the size-independence theorem of Section 2.2."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle.discretization import Grid, L_matrix
+from oracle import allatonce as aao
+from oracle import preconditioner as pc
+from oracle import minres as mr
+from oracle import examples as ex
+import synth
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "section3_tables.json")))
+T1 = {(r[0], r[1]): r for r in GOLD["table1"]["rows"]}
+T2 = {(r[0], r[1]): r for r in GOLD["table2"]["rows"]}
+
+
+def _example1(lt, lh):
+    g = Grid(2 ** lh - 1, 2 ** lh - 1, 2 ** lt)
+    src, psi0, psi1, exact = ex.example1_data(g)
+    f = aao.build_rhs(g, src, psi0, psi1)
+    return g, aao.reverse_time(f), exact, L_matrix(g)
+
+
+@pytest.mark.parametrize("lt,lh", [(4, 4), (5, 4), (6, 4), (7, 4), (4, 5), (5, 5), (6, 5), (7, 5), (4, 6)])
+def test_table1_and_table2_P_alpha(lt, lh):
+    """MINRES-P_alpha, alpha = 1e-6, tol 1e-6: 2 iterations (Table 1) and the
+    printed error of the iterate (Table 2) to three digits."""
+    g, b, exact, L = _example1(lt, lh)
+    res = mr.minres(lambda u: aao.apply_A(g, u, L), lambda y: pc.apply_Pinv(g, 1e-6, y), b, tol=1e-6, maxit=20)
+    assert res.converged
+    assert res.iters == T1[(lt, lh)][3] == 2
+    e = ex.error_E(g, res.x, exact)
+    want = T2[(lt, lh)][2]
+    assert abs(e - want) <= 0.006 * want, (e, want)
+
+
+def test_preconditioned_norm_rule_does_not_reproduce_table1():
+    """Documents the stopping-rule reading: the P^{-1}-norm rule needs 4 iterations
+    where Table 1 prints 2."""
+    g, b, _, L = _example1(4, 4)
+    res = mr.minres(lambda u: aao.apply_A(g, u, L), lambda y: pc.apply_Pinv(g, 1e-6, y), b,
+                    tol=1e-6, maxit=20, stop="precond")
+    assert res.iters == 4
+
+
+@pytest.mark.parametrize("lt,lh,exact_match", [(4, 4, True), (4, 5, True), (5, 4, False)])
+def test_table1_unpreconditioned(lt, lh, exact_match):
+    """MINRES-I column of Table 1 (614, 1992 reproduced exactly; 1204 within a few
+    iterations -- long unpreconditioned runs are sensitive to rounding order)."""
+    g, b, _, L = _example1(lt, lh)
+    res = mr.minres(lambda u: aao.apply_A(g, u, L), lambda y: y.copy(), b, tol=1e-6, maxit=5000)
+    want = T1[(lt, lh)][5]
+    if exact_match:
+        assert res.iters == want
+    else:
+        assert abs(res.iters - want) <= 4
+
+
+@pytest.mark.parametrize("lt,lh", [(4, 4), (4, 5)])
+def test_table1_abc_preconditioner(lt, lh):
+    """MINRES-P_1 (alpha = 1, the ABC preconditioner) column of Table 1 within 3%."""
+    g, b, _, L = _example1(lt, lh)
+    res = mr.minres(lambda u: aao.apply_A(g, u, L), lambda y: pc.apply_Pinv(g, 1.0, y, check_imag=False),
+                    b, tol=1e-6, maxit=2000)
+    want = T1[(lt, lh)][4]
+    assert abs(res.iters - want) <= 0.03 * want + 1
+
+
+@pytest.mark.parametrize("nx,ny,nt,alpha,k", [(6, 0, 8, 1e-2, 5), (3, 4, 6, 1e-3, 7), (5, 0, 16, 0.1, 9)])
+def test_iterates_match_scipy_and_brute_force(nx, ny, nt, alpha, k):
+    """x_k after exactly k iterations equals (a) scipy.sparse.linalg.minres with
+    maxiter=k and the same preconditioner, (b) the explicit Krylov minimiser of
+    ||b - A x||_{P^{-1}}.  The recurrence residual equals the explicit one and
+    |eta_j| is non-increasing."""
+    g = Grid(nx, ny, nt)
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal(g.shape)
+    A = (aao.assemble_Y(g) @ aao.assemble_T(g)).toarray()
+    Pinv = np.linalg.inv(pc.dense_P(g, alpha))
+    res = mr.minres(lambda u: aao.apply_A(g, u), lambda y: pc.apply_Pinv(g, alpha, y), b, fixed_iters=k)
+    xb = mr.krylov_minimiser(A, Pinv, b, k)
+    scale = np.max(np.abs(xb))
+    assert np.max(np.abs(res.x.reshape(-1) - xb)) < 1e-8 * scale
+    Mop = spla.LinearOperator((g.N, g.N), matvec=lambda y: pc.apply_Pinv(g, alpha, y.reshape(g.shape)).reshape(-1))
+    xs, _ = spla.minres(A, b.reshape(-1), rtol=1e-30, maxiter=k, M=Mop)
+    assert np.max(np.abs(res.x.reshape(-1) - xs)) < 1e-8 * scale
+    explicit = np.linalg.norm(b.reshape(-1) - A @ res.x.reshape(-1)) / np.linalg.norm(b)
+    assert abs(explicit - res.relres_history[-1]) < 1e-10
+    eta = np.array(res.eta_history)
+    assert np.all(np.diff(eta) <= 1e-12 * eta[0])
+
+
+def test_planted_sign_error_in_residual_recurrence_is_detected():
+    """A planted sign error in the operator handed to MINRES breaks the brute-force pin."""
+    g = Grid(6, 0, 8)
+    alpha, k = 1e-2, 4
+    b = np.random.default_rng(9).standard_normal(g.shape)
+    A = (aao.assemble_Y(g) @ aao.assemble_T(g)).toarray()
+    Pinv = np.linalg.inv(pc.dense_P(g, alpha))
+    xb = mr.krylov_minimiser(A, Pinv, b, k)
+
+    def bad_A(u):
+        return -aao.apply_A(g, u)
+    res = mr.minres(bad_A, lambda y: pc.apply_Pinv(g, alpha, y), b, fixed_iters=k)
+    assert np.max(np.abs(res.x.reshape(-1) - xb)) > 1e-3 * np.max(np.abs(xb))
+
+
+@pytest.mark.slow
+def test_size_independent_iterations():
+    """Theorem of Section 2.2: at fixed small alpha the iteration count does not grow
+    with the grid (random sources, tol 1e-8, alpha = 1e-3)."""
+    its = []
+    for n in (15, 31, 63):
+        g = Grid(n, n, n + 1)
+        src, psi0, psi1 = synth.random_source(n, n, n + 1, seed=2)
+        b = aao.reverse_time(aao.build_rhs(g, src, psi0, psi1))
+        L = L_matrix(g)
+        res = mr.minres(lambda u: aao.apply_A(g, u, L), lambda y: pc.apply_Pinv(g, 1e-3, y), b, tol=1e-8, maxit=100)
+        assert res.converged
+        its.append(res.iters)
+    assert max(its) - min(its) <= 2, its
+    assert max(its) <= 12, its
+
+
+def test_closed_form_solve_1d():
+    """MINRES-P_alpha on the 1D manufactured problem converges to the closed-form
+    discrete solution."""
+    nx, nt = 63, 64
+    g = Grid(nx, 0, nt)
+    src, psi0, psi1, _ = synth.manufactured_1d(nx, nt)
+    b = aao.reverse_time(aao.build_rhs(g, src, psi0, psi1))
+    res = mr.minres(lambda u: aao.apply_A(g, u), lambda y: pc.apply_Pinv(g, 1e-3, y), b, tol=1e-13, maxit=60)
+    lam = 1 + 2 * (g.tau / g.hx) ** 2 * np.sin(np.pi * g.hx / 2) ** 2
+    phi = np.arccos(1 / lam)
+    A = g.tau * np.pi / (lam * np.sin(phi))
+    (x,) = g.points()
+    u_cf = A * np.sin(np.arange(1, nt + 1) * phi)[:, None] * np.sin(np.pi * x)[None, :]
+    assert np.max(np.abs(res.x - u_cf)) < 1e-11
