@@ -1,0 +1,149 @@
+/* abac.h -- C ABI of the MI355X (gfx950) ABAC-preconditioned MINRES wave solver.
+ *
+ * The library solves the time-reversed all-at-once system Y T u = Y f of the
+ * implicit leap-frog discretisation of u_tt = Laplace(u) + f on (0,1)^d, d = 1, 2,
+ * with homogeneous Dirichlet data (Lin & Hon, Section 1, eqs. (1.1)-(1.4)), by
+ * MINRES preconditioned with the absolute-value block alpha-circulant matrix
+ * P_alpha = (C_alpha^{1/2})^T C_alpha^{1/2} (eqs. (1.5)-(1.10); fast apply in
+ * Section 2.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Grid: nx interior points in x (h = 1/(nx+1)); ny interior points in y, or
+ *   ny = 0 for the 1D problem; nt time levels, tau = T/nt.  Supported sizes:
+ *   nx+1 a power of two in [8, 4096] (1D) or [8, 512] (2D); ny+1 a power of two in
+ *   [8, 512] (2D); nt a power of two in [8, 1024].  Other sizes give ABAC_EINVAL.
+ * - Vectors are FP64 DEVICE pointers owned by the caller, laid out
+ *   [batch][nt][ny][nx] with x fastest (ny omitted in 1D); one vector holds
+ *   N = nt * nx * max(ny,1) values per right-hand side.  Level k (0-based) of a
+ *   solution vector is u^(k+1) of eq. (1.2).  Pointers must be 8-byte aligned and
+ *   must not alias unless stated.
+ * - Every call is asynchronous on the plan's HIP stream unless stated otherwise.
+ * - Calls return an abac_status and never throw; abac_last_error() returns a
+ *   thread-local description of the last failure.
+ * - A plan is bound to one stream and is not thread-safe; distinct plans are
+ *   independent and may run concurrently on different streams.
+ */
+#ifndef ABAC_H
+#define ABAC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct abac_plan abac_plan;
+
+typedef enum {
+  ABAC_OK = 0,
+  ABAC_EINVAL = -1,      /* bad argument or unsupported size                          */
+  ABAC_ENOMEM = -2,      /* device allocation failed or workspace too small           */
+  ABAC_EDEVICE = -3,     /* a HIP runtime call failed                                 */
+  ABAC_ENOTCONV = -4,    /* MINRES did not reach tol within maxit (last iterate kept) */
+  ABAC_EBREAKDOWN = -5,  /* <q, P^{-1} q> <= 0 or non-finite (e.g. NaN/Inf input)     */
+  ABAC_EBUDGET = -6,     /* server: request larger than the whole memory budget       */
+  ABAC_EAGAIN = -7       /* server: result not ready yet                              */
+} abac_status;
+
+typedef enum {
+  ABAC_PREC_FP64 = 0,    /* every transform of the preconditioner in FP64             */
+  ABAC_PREC_FP32 = 1     /* preconditioner transforms in FP32 complex; the Krylov
+                            recurrences, inner products and residual stay FP64        */
+} abac_prec;
+
+/* Bytes of device workspace a plan with these parameters needs (0 if invalid).
+ * batch = number of right-hand sides the plan processes per call (>= 1). */
+size_t abac_workspace_bytes(int nx, int ny, int nt, int prec, int batch);
+
+/* Create a plan for the grid (nx, ny, nt), final time T > 0 and alpha in (0, 1]
+ * (alpha = 1 is the absolute-value block circulant of the remark after eq. (1.10);
+ * alpha in (0,1) the ABAC preconditioner).  The spectral tables (DST eigenvalues
+ * of the Laplacian, alpha^{t/nt} scalings, FFT twiddles) are computed in FP64 on
+ * the host and copied into the workspace.
+ *   stream:      a hipStream_t (NULL = default stream); all work is enqueued there.
+ *   workspace:   device memory of at least abac_workspace_bytes(...) bytes owned by
+ *                the caller for the plan's lifetime, or NULL to let the library
+ *                allocate (and free at destroy) its own.
+ * Host-synchronous with respect to its table upload.  *out is set on success. */
+abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int prec, int batch,
+                             void *stream, void *workspace, size_t workspace_bytes, abac_plan **out);
+
+/* Release the plan (synchronises its stream; frees library-owned memory only). */
+abac_status abac_plan_destroy(abac_plan *plan);
+
+/* Right-hand side f of eq. (1.2) from source samples src = f^(0..nt-1)
+ * ([batch][nt][...]), initial displacement psi0 and velocity psi1 ([batch][...],
+ * one level each):  f_1 = tau^2 f^(0)/2 + tau psi1 + psi0,
+ * f_2 = tau^2 f^(1) - L psi0,  f_k = tau^2 f^(k-1) for k >= 3,
+ * with L = I - (tau^2/2) Laplace_h.  f must not alias the inputs. */
+abac_status abac_build_rhs(abac_plan *plan, const double *src, const double *psi0, const double *psi1,
+                           double *f);
+
+/* y = Y T x (eqs. (1.2), (1.4)): (T x)^(k) = L (x^(k) + x^(k-2)) - 2 x^(k-1), stored
+ * at level nt-1-k.  y must not alias x. */
+abac_status abac_apply_A(abac_plan *plan, const double *x, double *y);
+
+/* z = P_alpha^{-1} r = C_alpha^{-1/2} (C_alpha^{-1/2})^T r (eq. (1.9), Section 2.3),
+ * computed as S [K Y K Y] S with S the orthonormal DST-I in space and
+ * K = D^{-1} F^{-1} diag(mu^{-1/2}) F D per spatial mode in time (the transposed
+ * factor uses (C^{-1/2})^T = Y C^{-1/2} Y).  z may alias r. */
+abac_status abac_apply_Pinv(abac_plan *plan, const double *r, double *z);
+
+/* Solve Y T u = Y f for every right-hand side in the batch by preconditioned MINRES
+ * with zero initial guess (Section 3).  Stops a right-hand side at the first
+ * iteration whose residual ||Y f - Y T u||_2 <= tol ||Y f||_2 (tracked by the MINRES
+ * residual recurrence and confirmed explicitly; iterations continue with explicit
+ * checks if the confirmation fails).  Host-synchronous.  f must stay valid and
+ * unchanged during the call; u receives the iterates.
+ *   iters, relres, status: host arrays of length batch (status may be NULL) that
+ *   receive per right-hand side the iteration count, the explicit relative residual
+ *   and the status (ABAC_OK, ABAC_ENOTCONV with the last iterate in u, or
+ *   ABAC_EBREAKDOWN).
+ * Returns ABAC_OK if every right-hand side converged, otherwise the first failing
+ * status. */
+abac_status abac_minres_solve(abac_plan *plan, const double *f, double *u, double tol, int maxit,
+                              int *iters, double *relres, int *status);
+
+/* Asynchronous form of abac_minres_solve for overlapping solves on several plans:
+ * begin() enqueues the set-up, advance(k) enqueues k more iterations (right-hand
+ * sides that have stopped skip their work on the device), poll() reports without
+ * blocking whether every right-hand side of the plan has stopped as of the last
+ * completed poll point (*done = 1) and finish() waits and fills the per-RHS results
+ * like abac_minres_solve. */
+abac_status abac_minres_begin(abac_plan *plan, const double *f, double *u, double tol, int maxit);
+abac_status abac_minres_advance(abac_plan *plan, int iterations);
+abac_status abac_minres_poll(abac_plan *plan, int *done);
+abac_status abac_minres_finish(abac_plan *plan, int *iters, double *relres, int *status);
+
+/* Kernel-time accounting (for roofline reports).  When enabled, every kernel the
+ * plan launches is bracketed by HIP events on the plan stream.  read() synchronises
+ * the stream and returns, for kernel class k (see ABAC_K_*), the summed duration in
+ * milliseconds and the number of launches since the last reset. */
+enum {
+  ABAC_K_STENCIL = 0,   /* Y T x matvec (and the fused <A z, z>)        */
+  ABAC_K_DSTX_FWD = 1,  /* first spatial DST pass (x)                   */
+  ABAC_K_DSTY = 2,      /* y-direction DST pass (2D, both directions)   */
+  ABAC_K_TIME = 3,      /* per-mode time pipeline K Y K Y               */
+  ABAC_K_DSTX_INV = 4,  /* last spatial DST pass (x)                    */
+  ABAC_K_UPDATE = 5,    /* MINRES w / x / r update and ||r||^2          */
+  ABAC_K_RESIDUAL = 6,  /* explicit residual check                      */
+  ABAC_K_INIT = 7,      /* solve set-up                                 */
+  ABAC_K_RHS = 8,       /* right-hand side assembly                     */
+  ABAC_K_COUNT = 9
+};
+abac_status abac_profile_enable(abac_plan *plan, int on);
+abac_status abac_profile_read(abac_plan *plan, int kernel, double *total_ms, long long *launches);
+abac_status abac_profile_reset(abac_plan *plan);
+
+/* Constant string for a status code. */
+const char *abac_status_string(int status);
+
+/* Thread-local description of the last error ("" if none). */
+const char *abac_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABAC_H */

@@ -1,0 +1,220 @@
+"""Thin Python binding of ``libabac.so`` (the C ABI declared in ``include/abac.h``).
+
+Argument marshalling only: every step of the solver runs in the HIP library.  PyTorch
+supplies device memory (the plan workspace and all vectors are torch tensors on the
+GPU) and the HIP stream.  There is no fallback: if the library is not built or no
+GPU is present, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libabac.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, EBUDGET, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7
+PREC = {"fp64": 0, "fp32": 1}
+KERNELS = {"stencil": 0, "dstx_fwd": 1, "dsty": 2, "time": 3, "dstx_inv": 4, "update": 5,
+           "residual": 6, "init": 7, "rhs": 8}
+
+EXPORTED = [
+    "abac_workspace_bytes", "abac_plan_create", "abac_plan_destroy", "abac_build_rhs", "abac_apply_A",
+    "abac_apply_Pinv", "abac_minres_solve", "abac_minres_begin", "abac_minres_advance", "abac_minres_poll",
+    "abac_minres_finish", "abac_profile_enable", "abac_profile_read", "abac_profile_reset",
+    "abac_status_string", "abac_last_error",
+]
+
+_lib = None
+
+
+class AbacError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libabac.so and declare the C signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run paper_2306_03574_amd.build.build() first")
+    lib = ctypes.CDLL(path)
+    P, I, D, SZ, VP = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
+    lib.abac_workspace_bytes.argtypes = [I, I, I, I, I]
+    lib.abac_workspace_bytes.restype = SZ
+    lib.abac_plan_create.argtypes = [I, I, I, D, D, I, I, VP, VP, SZ, ctypes.POINTER(P)]
+    lib.abac_plan_create.restype = I
+    lib.abac_plan_destroy.argtypes = [P]
+    lib.abac_plan_destroy.restype = I
+    lib.abac_build_rhs.argtypes = [P, VP, VP, VP, VP]
+    lib.abac_build_rhs.restype = I
+    lib.abac_apply_A.argtypes = [P, VP, VP]
+    lib.abac_apply_A.restype = I
+    lib.abac_apply_Pinv.argtypes = [P, VP, VP]
+    lib.abac_apply_Pinv.restype = I
+    lib.abac_minres_solve.argtypes = [P, VP, VP, D, I, VP, VP, VP]
+    lib.abac_minres_solve.restype = I
+    lib.abac_minres_begin.argtypes = [P, VP, VP, D, I]
+    lib.abac_minres_begin.restype = I
+    lib.abac_minres_advance.argtypes = [P, I]
+    lib.abac_minres_advance.restype = I
+    lib.abac_minres_poll.argtypes = [P, ctypes.POINTER(I)]
+    lib.abac_minres_poll.restype = I
+    lib.abac_minres_finish.argtypes = [P, VP, VP, VP]
+    lib.abac_minres_finish.restype = I
+    lib.abac_profile_enable.argtypes = [P, I]
+    lib.abac_profile_enable.restype = I
+    lib.abac_profile_read.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]
+    lib.abac_profile_read.restype = I
+    lib.abac_profile_reset.argtypes = [P]
+    lib.abac_profile_reset.restype = I
+    lib.abac_status_string.argtypes = [I]
+    lib.abac_status_string.restype = ctypes.c_char_p
+    lib.abac_last_error.argtypes = []
+    lib.abac_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str, ok=(OK,)):
+    if status not in ok:
+        lib = load_library()
+        raise AbacError(status, f"{what}: {lib.abac_status_string(status).decode()} "
+                                f"({lib.abac_last_error().decode()})")
+    return status
+
+
+def workspace_bytes(nx: int, ny: int, nt: int, prec: str = "fp64", batch: int = 1) -> int:
+    return int(load_library().abac_workspace_bytes(nx, ny, nt, PREC[prec], batch))
+
+
+class Plan:
+    """A solver plan for one grid (nx, ny, nt), final time T and alpha, with a fixed
+    batch of right-hand sides, bound to a torch CUDA (HIP) stream."""
+
+    def __init__(self, nx: int, ny: int, nt: int, T: float = 1.0, alpha: float = 1e-3, prec: str = "fp64",
+                 batch: int = 1, device="cuda:0", stream: torch.cuda.Stream | None = None):
+        lib = load_library()
+        self.device = torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("the ABAC library needs a GPU (torch.cuda is not available)")
+        self.nx, self.ny, self.nt, self.T, self.alpha, self.prec, self.batch = nx, ny, nt, T, alpha, prec, batch
+        self.level_shape = (ny, nx) if ny else (nx,)
+        self.shape = (batch, nt) + self.level_shape
+        self.N = nt * nx * (ny if ny else 1)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = lib.abac_workspace_bytes(nx, ny, nt, PREC[prec], batch)
+        if nbytes == 0:
+            raise AbacError(EINVAL, f"unsupported problem nx={nx} ny={ny} nt={nt} prec={prec} batch={batch}")
+        self.workspace = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.abac_plan_create(nx, ny, nt, float(T), float(alpha), PREC[prec], batch,
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.c_void_p(aligned),
+                                        ctypes.c_size_t(nbytes), ctypes.byref(handle)), "abac_plan_create")
+        self._h = handle
+        self._lib = lib
+        self._f = None
+        self._u = None
+
+    # -- helpers ---------------------------------------------------------------
+    def _vec(self, t: torch.Tensor, name: str) -> ctypes.c_void_p:
+        if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != torch.float64:
+            raise TypeError(f"{name} must be a float64 tensor on {self.device}")
+        if not t.is_contiguous() or t.numel() != self.batch * self.N:
+            raise ValueError(f"{name} must be contiguous with {self.batch * self.N} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _level(self, t: torch.Tensor, name: str) -> ctypes.c_void_p:
+        m = self.N // self.nt
+        if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != torch.float64:
+            raise TypeError(f"{name} must be a float64 tensor on {self.device}")
+        if not t.is_contiguous() or t.numel() != self.batch * m:
+            raise ValueError(f"{name} must be contiguous with {self.batch * m} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def empty(self) -> torch.Tensor:
+        return torch.empty(self.shape, dtype=torch.float64, device=self.device)
+
+    # -- operators -------------------------------------------------------------
+    def build_rhs(self, src, psi0, psi1, f=None):
+        f = self.empty() if f is None else f
+        _check(self._lib.abac_build_rhs(self._h, self._vec(src, "src"), self._level(psi0, "psi0"),
+                                        self._level(psi1, "psi1"), self._vec(f, "f")), "abac_build_rhs")
+        return f
+
+    def apply_A(self, x, y=None):
+        y = self.empty() if y is None else y
+        _check(self._lib.abac_apply_A(self._h, self._vec(x, "x"), self._vec(y, "y")), "abac_apply_A")
+        return y
+
+    def apply_Pinv(self, r, z=None):
+        z = self.empty() if z is None else z
+        _check(self._lib.abac_apply_Pinv(self._h, self._vec(r, "r"), self._vec(z, "z")), "abac_apply_Pinv")
+        return z
+
+    def solve(self, f, u=None, tol: float = 1e-8, maxit: int = 500):
+        """MINRES on Y T u = Y f.  Returns (u, iters[list], relres[list], status[list])."""
+        u = self.empty() if u is None else u
+        iters = (ctypes.c_int * self.batch)()
+        relres = (ctypes.c_double * self.batch)()
+        status = (ctypes.c_int * self.batch)()
+        _check(self._lib.abac_minres_solve(self._h, self._vec(f, "f"), self._vec(u, "u"), float(tol), int(maxit),
+                                           iters, relres, status), "abac_minres_solve",
+               ok=(OK, ENOTCONV, EBREAKDOWN))
+        return u, list(iters), list(relres), list(status)
+
+    # -- asynchronous solve ----------------------------------------------------
+    def begin(self, f, u, tol: float = 1e-8, maxit: int = 500):
+        self._f, self._u = f, u
+        _check(self._lib.abac_minres_begin(self._h, self._vec(f, "f"), self._vec(u, "u"), float(tol), int(maxit)),
+               "abac_minres_begin")
+
+    def advance(self, iterations: int = 1):
+        _check(self._lib.abac_minres_advance(self._h, int(iterations)), "abac_minres_advance")
+
+    def poll(self) -> bool:
+        d = ctypes.c_int(0)
+        _check(self._lib.abac_minres_poll(self._h, ctypes.byref(d)), "abac_minres_poll")
+        return bool(d.value)
+
+    def finish(self):
+        iters = (ctypes.c_int * self.batch)()
+        relres = (ctypes.c_double * self.batch)()
+        status = (ctypes.c_int * self.batch)()
+        _check(self._lib.abac_minres_finish(self._h, iters, relres, status), "abac_minres_finish",
+               ok=(OK, ENOTCONV, EBREAKDOWN))
+        self._f = None
+        return list(iters), list(relres), list(status)
+
+    # -- kernel timing -----------------------------------------------------------
+    def profile(self, on: bool = True):
+        _check(self._lib.abac_profile_enable(self._h, 1 if on else 0), "abac_profile_enable")
+
+    def profile_read(self, kernel: str):
+        ms = ctypes.c_double(0)
+        n = ctypes.c_longlong(0)
+        _check(self._lib.abac_profile_read(self._h, KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)),
+               "abac_profile_read")
+        return ms.value, n.value
+
+    def profile_reset(self):
+        _check(self._lib.abac_profile_reset(self._h), "abac_profile_reset")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            self._lib.abac_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

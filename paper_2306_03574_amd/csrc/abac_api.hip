@@ -1,0 +1,547 @@
+// Host side of the ABAC library: plan creation (FP64 spectral tables), workspace
+// layout, the C ABI entry points and the MINRES launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/abac.h"
+#include "abac_internal.h"
+
+using namespace abac;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+abac_status fail(abac_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+abac_status hip_fail(hipError_t e, const char* where) {
+  return fail(ABAC_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                    \
+  do {                                                   \
+    hipError_t e_ = (expr);                              \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);    \
+  } while (0)
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t twx, twy, twt, beta, abk, sc, sci, scratch, vec[8], st, partials, counters, total;
+};
+
+// Validate the problem and fill the size fields of a DevPlan.
+abac_status describe(int nx, int ny, int nt, double T, double alpha, int prec, int batch, DevPlan& P) {
+  if (prec != ABAC_PREC_FP64 && prec != ABAC_PREC_FP32) return fail(ABAC_EINVAL, "prec must be 0 (FP64) or 1 (FP32)");
+  if (batch < 1) return fail(ABAC_EINVAL, "batch must be >= 1");
+  if (!(T > 0) || !std::isfinite(T)) return fail(ABAC_EINVAL, "T must be positive and finite");
+  if (!(alpha > 0) || !(alpha <= 1)) return fail(ABAC_EINVAL, "alpha must be in (0, 1]");
+  if (!is_pow2(nt) || nt < 8 || nt > 1024) return fail(ABAC_EINVAL, "nt must be a power of two in [8, 1024]");
+  if (ny < 0) return fail(ABAC_EINVAL, "ny must be >= 0");
+  const int Mx = nx + 1;
+  if (!is_pow2(Mx) || Mx < 8 || Mx > (ny ? 512 : 4096))
+    return fail(ABAC_EINVAL, ny ? "nx+1 must be a power of two in [8, 512] in 2D" : "nx+1 must be a power of two in [8, 4096] in 1D");
+  if (ny) {
+    const int My = ny + 1;
+    if (!is_pow2(My) || My < 8 || My > 512) return fail(ABAC_EINVAL, "ny+1 must be a power of two in [8, 512]");
+  }
+  std::memset(&P, 0, sizeof(P));
+  P.nx = nx;
+  P.ny = ny;
+  P.nt = nt;
+  P.B = batch;
+  P.ny1 = ny ? ny : 1;
+  P.Mx = Mx;
+  P.My = ny ? ny + 1 : 1;
+  P.m = nx * P.ny1;
+  P.ms = Mx * P.ny1;
+  P.N = (long long)nt * P.m;
+  P.NS = (long long)nt * P.ms;
+  const double hx = 1.0 / Mx;
+  const double tau = T / nt;
+  P.tau = tau;
+  P.tau2 = tau * tau;
+  P.cx = 0.5 * tau * tau / (hx * hx);
+  P.cy = 0.0;
+  P.c0 = 1.0 + 2.0 * P.cx;
+  if (ny) {
+    const double hy = 1.0 / (ny + 1);
+    P.cy = 0.5 * tau * tau / (hy * hy);
+    P.c0 += 2.0 * P.cy;
+  }
+  P.maxparts = std::max(stencil_blocks(P), std::max(update_blocks(P), dstx_blocks(P, prec)));
+  return ABAC_OK;
+}
+
+Layout make_layout(const DevPlan& P, int prec) {
+  Layout Lo{};
+  const size_t real = prec ? sizeof(float) : sizeof(double);
+  const size_t cplx = 2 * real;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
+  Lo.twx = take(cplx * 2 * P.Mx);
+  Lo.twy = take(cplx * 2 * P.My);
+  Lo.twt = take(cplx * P.nt);
+  Lo.beta = take(real * P.ms);
+  Lo.abk = take(cplx * 2 * P.nt);
+  Lo.sc = take(real * P.nt);
+  Lo.sci = take(real * P.nt);
+  Lo.scratch = take(real * (size_t)P.NS * P.B);
+  for (int i = 0; i < 8; ++i) Lo.vec[i] = take(sizeof(double) * (size_t)P.N * P.B);
+  Lo.st = take(sizeof(MinresState) * P.B);
+  Lo.partials = take(sizeof(double) * (size_t)P.maxparts * P.B);
+  Lo.counters = take(sizeof(unsigned) * P.B);
+  Lo.total = o;
+  return Lo;
+}
+
+struct ProfPair {
+  int kid;
+  hipEvent_t e0, e1;
+};
+
+constexpr int kRing = 16;
+
+}  // namespace
+
+struct abac_plan {
+  DevPlan P;
+  int prec;
+  double T, alpha;
+  hipStream_t stream;
+  void* ws;
+  size_t ws_bytes;
+  bool own_ws;
+  // asynchronous solve bookkeeping
+  MinresState* h_ring;   // pinned, kRing * B states
+  hipEvent_t ring_ev[kRing];
+  long long ring_posted;  // number of state snapshots enqueued
+  const double* f;
+  double* u;
+  bool active;
+  // kernel timing
+  bool prof;
+  std::vector<ProfPair> pending;
+  double prof_ms[ABAC_K_COUNT];
+  long long prof_n[ABAC_K_COUNT];
+};
+
+namespace {
+
+template <typename F>
+abac_status run_kernel(abac_plan* p, int kid, F&& launch, const char* what) {
+  ProfPair pp{kid, nullptr, nullptr};
+  if (p->prof) {
+    HIP_TRY(hipEventCreate(&pp.e0));
+    HIP_TRY(hipEventCreate(&pp.e1));
+    HIP_TRY(hipEventRecord(pp.e0, p->stream));
+  }
+  hipError_t e = launch();
+  if (e != hipSuccess) return hip_fail(e, what);
+  if (p->prof) {
+    HIP_TRY(hipEventRecord(pp.e1, p->stream));
+    p->pending.push_back(pp);
+  }
+  return ABAC_OK;
+}
+
+abac_status flush_prof(abac_plan* p) {
+  if (p->pending.empty()) return ABAC_OK;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  for (auto& pp : p->pending) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, pp.e0, pp.e1));
+    p->prof_ms[pp.kid] += ms;
+    p->prof_n[pp.kid] += 1;
+    (void)hipEventDestroy(pp.e0);
+    (void)hipEventDestroy(pp.e1);
+  }
+  p->pending.clear();
+  return ABAC_OK;
+}
+
+#define RUN(kid, expr)                                            \
+  do {                                                            \
+    abac_status s_ = run_kernel(p, kid, [&] { return (expr); }, #expr); \
+    if (s_ != ABAC_OK) return s_;                                 \
+  } while (0)
+
+// z = P^{-1} r on the plan stream.  In MINRES mode (init != 0 or iter != 0) the
+// first pass reads V_1 (init) or forms the Lanczos vector (iteration) and the last
+// pass writes Z and finishes the scalar update.
+abac_status enqueue_pinv(abac_plan* p, const double* r, double* z, int minres_mode) {
+  const DevPlan& P = p->P;
+  const int check = minres_mode != 0;
+  const int fwd_mode = minres_mode == 2 ? FWD_LANCZOS : FWD_PLAIN;
+  const double* in = minres_mode == 1 ? P.V[1] : r;
+  RUN(ABAC_K_DSTX_FWD, launch_dstx_fwd(P, p->prec, fwd_mode, check, in, p->stream));
+  if (P.ny) RUN(ABAC_K_DSTY, launch_dsty(P, p->prec, check, p->stream));
+  RUN(ABAC_K_TIME, launch_time(P, p->prec, check, p->stream));
+  if (P.ny) RUN(ABAC_K_DSTY, launch_dsty(P, p->prec, check, p->stream));
+  const int inv_mode = minres_mode == 0 ? INV_PLAIN : (minres_mode == 1 ? INV_GAMMA_INIT : INV_GAMMA_ITER);
+  RUN(ABAC_K_DSTX_INV, launch_dstx_inv(P, p->prec, inv_mode, z, p->stream));
+  return ABAC_OK;
+}
+
+abac_status enqueue_iteration(abac_plan* p) {
+  const DevPlan& P = p->P;
+  RUN(ABAC_K_STENCIL, launch_stencil(P, STENCIL_MINRES, nullptr, nullptr, nullptr, p->stream));
+  abac_status s = enqueue_pinv(p, nullptr, nullptr, 2);
+  if (s != ABAC_OK) return s;
+  RUN(ABAC_K_UPDATE, launch_update(P, p->u, p->stream));
+  RUN(ABAC_K_RESIDUAL, launch_stencil(P, STENCIL_RESIDUAL, p->u, nullptr, p->f, p->stream));
+  return ABAC_OK;
+}
+
+abac_status post_snapshot(abac_plan* p) {
+  const int slot = (int)(p->ring_posted % kRing);
+  HIP_TRY(hipMemcpyAsync(p->h_ring + (size_t)slot * p->P.B, p->P.st, sizeof(MinresState) * p->P.B,
+                         hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipEventRecord(p->ring_ev[slot], p->stream));
+  p->ring_posted++;
+  return ABAC_OK;
+}
+
+bool all_stopped(const MinresState* s, int B) {
+  for (int b = 0; b < B; ++b)
+    if (s[b].state == ST_RUNNING) return false;
+  return true;
+}
+
+void fill_results(const MinresState* s, int B, int* iters, double* relres, int* status, abac_status* worst) {
+  *worst = ABAC_OK;
+  for (int b = 0; b < B; ++b) {
+    if (iters) iters[b] = s[b].iter;
+    if (relres) relres[b] = s[b].bnorm2 > 0 ? std::sqrt(s[b].res2 / s[b].bnorm2) : 0.0;
+    int st = s[b].state == ST_DONE ? s[b].status : ABAC_ENOTCONV;
+    if (status) status[b] = st;
+    if (st != ABAC_OK && *worst == ABAC_OK) *worst = (abac_status)st;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t abac_workspace_bytes(int nx, int ny, int nt, int prec, int batch) {
+  DevPlan P;
+  if (describe(nx, ny, nt, 1.0, 0.5, prec, batch, P) != ABAC_OK) return 0;
+  return make_layout(P, prec).total;
+}
+
+abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int prec, int batch, void* stream,
+                             void* workspace, size_t workspace_bytes, abac_plan** out) {
+  g_last_error.clear();
+  if (!out) return fail(ABAC_EINVAL, "out is NULL");
+  *out = nullptr;
+  DevPlan P;
+  abac_status s = describe(nx, ny, nt, T, alpha, prec, batch, P);
+  if (s != ABAC_OK) return s;
+  // LDS limit of the device for the largest transform block
+  int dev = 0, maxlds = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const size_t need = std::max(transform_lds_bytes(2 * P.Mx, prec),
+                               std::max(transform_lds_bytes(nt, prec), ny ? transform_lds_bytes(2 * P.My, prec) : 0));
+  if (need + 1024 > (size_t)maxlds)
+    return fail(ABAC_EINVAL, "transform needs " + std::to_string(need) + " B of LDS, device allows " +
+                                 std::to_string(maxlds) + " (use the FP32 preconditioner for this size)");
+  const Layout Lo = make_layout(P, prec);
+  void* ws = workspace;
+  bool own = false;
+  if (!ws) {
+    hipError_t e = hipMalloc(&ws, Lo.total);
+    if (e != hipSuccess) return fail(ABAC_ENOMEM, "hipMalloc of " + std::to_string(Lo.total) + " bytes failed");
+    own = true;
+  } else if (workspace_bytes < Lo.total) {
+    return fail(ABAC_ENOMEM, "workspace too small: need " + std::to_string(Lo.total) + " bytes");
+  } else if (((uintptr_t)ws & 255) != 0) {
+    return fail(ABAC_EINVAL, "workspace must be 256-byte aligned");
+  }
+  char* base = static_cast<char*>(ws);
+  P.twx = base + Lo.twx;
+  P.twy = base + Lo.twy;
+  P.twt = base + Lo.twt;
+  P.beta = base + Lo.beta;
+  P.abk = base + Lo.abk;
+  P.sc = base + Lo.sc;
+  P.sci = base + Lo.sci;
+  P.scratch = base + Lo.scratch;
+  for (int i = 0; i < 3; ++i) P.V[i] = reinterpret_cast<double*>(base + Lo.vec[i]);
+  for (int i = 0; i < 2; ++i) P.Z[i] = reinterpret_cast<double*>(base + Lo.vec[3 + i]);
+  for (int i = 0; i < 2; ++i) P.W[i] = reinterpret_cast<double*>(base + Lo.vec[5 + i]);
+  P.R = reinterpret_cast<double*>(base + Lo.vec[7]);
+  P.st = reinterpret_cast<MinresState*>(base + Lo.st);
+  P.partials = reinterpret_cast<double*>(base + Lo.partials);
+  P.counters = reinterpret_cast<unsigned*>(base + Lo.counters);
+
+  // ---- spectral tables in FP64 --------------------------------------------
+  const double pi = 3.14159265358979323846;
+  const int Mx = P.Mx, My = P.My;
+  std::vector<double> twx(4 * Mx), twy(4 * My), twt(2 * nt), beta(P.ms), abk(4 * nt), sc(nt), sci(nt);
+  auto twiddles = [&](std::vector<double>& t, int L) {
+    for (int e = 0; e < L; ++e) {
+      // exp(-2 pi i e / L), symmetric evaluation to keep the table accurate
+      const double ang = 2.0 * pi * (double)e / (double)L;
+      t[2 * e] = std::cos(ang);
+      t[2 * e + 1] = -std::sin(ang);
+    }
+  };
+  twiddles(twx, 2 * Mx);
+  twiddles(twy, 2 * My);
+  twiddles(twt, nt);
+  // (tau^2/2) times the eigenvalues of -Laplace_h in the sine basis:
+  // (4/h^2) sin^2(j pi h / 2), summed over the axes; pad column gets 1 (harmless)
+  const double hx = 1.0 / Mx, hy = ny ? 1.0 / My : 0.0;
+  std::vector<double> kx(nx), ky(ny ? ny : 1, 0.0);
+  for (int j = 0; j < nx; ++j) {
+    const double sj = std::sin((j + 1) * pi * hx / 2.0);
+    kx[j] = 4.0 / (hx * hx) * sj * sj;
+  }
+  for (int j = 0; j < ny; ++j) {
+    const double sj = std::sin((j + 1) * pi * hy / 2.0);
+    ky[j] = 4.0 / (hy * hy) * sj * sj;
+  }
+  for (int yy = 0; yy < P.ny1; ++yy)
+    for (int xx = 0; xx < Mx; ++xx)
+      beta[(size_t)yy * Mx + xx] = xx < nx ? 0.5 * P.tau2 * (kx[xx] + (ny ? ky[yy] : 0.0)) : 1.0;
+  // mu_{k}(beta) = A_k + beta B_k with A_k = (1 - a w_k)^2, B_k = 1 + a^2 w_k^2,
+  // w_k = exp(-2 pi i k/nt), a = alpha^{1/nt}; 1 - a w_k evaluated without
+  // cancellation as ((1-a) + 2 a sin^2(th/2)) + i a sin(th).
+  const double la = std::log(alpha) / nt;
+  const double a = std::exp(la);
+  const double oma = -std::expm1(la);
+  double mu_min = 1e300;
+  for (int k = 0; k < nt; ++k) {
+    const double th = 2.0 * pi * k / nt;
+    const double sh = std::sin(0.5 * th);
+    const double re = oma + 2.0 * a * sh * sh, im = a * std::sin(th);
+    abk[4 * k + 0] = re * re - im * im;
+    abk[4 * k + 1] = 2.0 * re * im;
+    abk[4 * k + 2] = 1.0 + a * a * std::cos(2.0 * th);
+    abk[4 * k + 3] = -a * a * std::sin(2.0 * th);
+    sc[k] = std::exp(la * k);
+    sci[k] = std::exp(-la * k);
+  }
+  if (alpha > 0.5) {
+    // C_alpha can be (nearly) singular as alpha -> 1 (remark on Strang's circulant);
+    // reject plans whose spectrum touches zero.
+    double mu_max = 0.0;
+    for (int k = 0; k < nt; ++k)
+      for (size_t q = 0; q < (size_t)P.ms; ++q) {
+        if (q % Mx == (size_t)(Mx - 1)) continue;
+        const double mr = abk[4 * k] + beta[q] * abk[4 * k + 2], mi = abk[4 * k + 1] + beta[q] * abk[4 * k + 3];
+        const double mag = std::hypot(mr, mi);
+        mu_min = std::min(mu_min, mag);
+        mu_max = std::max(mu_max, mag);
+      }
+    if (mu_min <= 1e-12 * mu_max) {
+      if (own) (void)hipFree(ws);
+      return fail(ABAC_EINVAL, "C_alpha is numerically singular for this alpha and grid");
+    }
+  }
+  auto upload = [&](const void* dst, const std::vector<double>& v) -> hipError_t {
+    if (prec == ABAC_PREC_FP64) return hipMemcpy(const_cast<void*>(dst), v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
+    std::vector<float> f(v.begin(), v.end());
+    return hipMemcpy(const_cast<void*>(dst), f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = upload(P.twx, twx);
+  if (e == hipSuccess) e = upload(P.twy, twy);
+  if (e == hipSuccess) e = upload(P.twt, twt);
+  if (e == hipSuccess) e = upload(P.beta, beta);
+  if (e == hipSuccess) e = upload(P.abk, abk);
+  if (e == hipSuccess) e = upload(P.sc, sc);
+  if (e == hipSuccess) e = upload(P.sci, sci);
+  if (e == hipSuccess) e = hipMemset(P.counters, 0, sizeof(unsigned) * batch);
+  if (e == hipSuccess) e = hipMemset(P.st, 0, sizeof(MinresState) * batch);
+  if (e == hipSuccess) e = hipMemset(P.scratch, 0, (prec ? 4 : 8) * (size_t)P.NS * batch);
+  if (e != hipSuccess) {
+    if (own) (void)hipFree(ws);
+    return hip_fail(e, "table upload");
+  }
+  abac_plan* p = new abac_plan();
+  p->P = P;
+  p->prec = prec;
+  p->T = T;
+  p->alpha = alpha;
+  p->stream = static_cast<hipStream_t>(stream);
+  p->ws = ws;
+  p->ws_bytes = Lo.total;
+  p->own_ws = own;
+  p->h_ring = nullptr;
+  e = hipHostMalloc(reinterpret_cast<void**>(&p->h_ring), sizeof(MinresState) * (size_t)kRing * batch, hipHostMallocDefault);
+  for (int i = 0; e == hipSuccess && i < kRing; ++i) e = hipEventCreateWithFlags(&p->ring_ev[i], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (own) (void)hipFree(ws);
+    delete p;
+    return hip_fail(e, "host ring");
+  }
+  p->ring_posted = 0;
+  p->f = nullptr;
+  p->u = nullptr;
+  p->active = false;
+  p->prof = false;
+  for (int k = 0; k < ABAC_K_COUNT; ++k) {
+    p->prof_ms[k] = 0;
+    p->prof_n[k] = 0;
+  }
+  *out = p;
+  return ABAC_OK;
+}
+
+abac_status abac_plan_destroy(abac_plan* p) {
+  if (!p) return ABAC_OK;
+  (void)hipStreamSynchronize(p->stream);
+  flush_prof(p);
+  for (int i = 0; i < kRing; ++i) (void)hipEventDestroy(p->ring_ev[i]);
+  if (p->h_ring) (void)hipHostFree(p->h_ring);
+  if (p->own_ws) (void)hipFree(p->ws);
+  delete p;
+  return ABAC_OK;
+}
+
+abac_status abac_build_rhs(abac_plan* p, const double* src, const double* psi0, const double* psi1, double* f) {
+  if (!p || !src || !psi0 || !psi1 || !f) return fail(ABAC_EINVAL, "NULL argument");
+  RUN(ABAC_K_RHS, launch_rhs(p->P, src, psi0, psi1, f, p->stream));
+  return ABAC_OK;
+}
+
+abac_status abac_apply_A(abac_plan* p, const double* x, double* y) {
+  if (!p || !x || !y) return fail(ABAC_EINVAL, "NULL argument");
+  if (x == y) return fail(ABAC_EINVAL, "apply_A: y must not alias x");
+  RUN(ABAC_K_STENCIL, launch_stencil(p->P, STENCIL_PLAIN, x, y, nullptr, p->stream));
+  return ABAC_OK;
+}
+
+abac_status abac_apply_Pinv(abac_plan* p, const double* r, double* z) {
+  if (!p || !r || !z) return fail(ABAC_EINVAL, "NULL argument");
+  return enqueue_pinv(p, r, z, 0);
+}
+
+abac_status abac_minres_begin(abac_plan* p, const double* f, double* u, double tol, int maxit) {
+  if (!p || !f || !u) return fail(ABAC_EINVAL, "NULL argument");
+  if (!(tol > 0) || maxit < 1) return fail(ABAC_EINVAL, "tol must be > 0 and maxit >= 1");
+  if (f == u) return fail(ABAC_EINVAL, "u must not alias f");
+  p->f = f;
+  p->u = u;
+  p->active = true;
+  RUN(ABAC_K_INIT, launch_init(p->P, f, u, tol, maxit, p->stream));
+  abac_status s = enqueue_pinv(p, nullptr, nullptr, 1);
+  if (s != ABAC_OK) return s;
+  return post_snapshot(p);
+}
+
+abac_status abac_minres_advance(abac_plan* p, int iterations) {
+  if (!p || !p->active) return fail(ABAC_EINVAL, "no solve in progress");
+  for (int i = 0; i < iterations; ++i) {
+    abac_status s = enqueue_iteration(p);
+    if (s != ABAC_OK) return s;
+  }
+  return post_snapshot(p);
+}
+
+abac_status abac_minres_poll(abac_plan* p, int* done) {
+  if (!p || !done) return fail(ABAC_EINVAL, "NULL argument");
+  *done = 0;
+  if (!p->active) {
+    *done = 1;
+    return ABAC_OK;
+  }
+  // newest completed snapshot
+  for (long long k = p->ring_posted - 1; k >= 0 && k >= p->ring_posted - kRing; --k) {
+    const int slot = (int)(k % kRing);
+    hipError_t e = hipEventQuery(p->ring_ev[slot]);
+    if (e == hipSuccess) {
+      *done = all_stopped(p->h_ring + (size_t)slot * p->P.B, p->P.B) ? 1 : 0;
+      return ABAC_OK;
+    }
+    if (e != hipErrorNotReady) return hip_fail(e, "hipEventQuery");
+  }
+  return ABAC_OK;
+}
+
+abac_status abac_minres_finish(abac_plan* p, int* iters, double* relres, int* status) {
+  if (!p || !p->active) return fail(ABAC_EINVAL, "no solve in progress");
+  RUN(ABAC_K_RESIDUAL, launch_stencil(p->P, STENCIL_REPORT, p->u, nullptr, p->f, p->stream));
+  std::vector<MinresState> h(p->P.B);
+  HIP_TRY(hipMemcpyAsync(h.data(), p->P.st, sizeof(MinresState) * p->P.B, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  p->active = false;
+  abac_status worst;
+  fill_results(h.data(), p->P.B, iters, relres, status, &worst);
+  return worst;
+}
+
+abac_status abac_minres_solve(abac_plan* p, const double* f, double* u, double tol, int maxit, int* iters,
+                              double* relres, int* status) {
+  abac_status s = abac_minres_begin(p, f, u, tol, maxit);
+  if (s != ABAC_OK) return s;
+  const int lag = 2;  // iterations kept queued ahead of the newest observed state
+  for (int it = 0; it < maxit; ++it) {
+    s = abac_minres_advance(p, 1);
+    if (s != ABAC_OK) return s;
+    const long long want = p->ring_posted - 1 - lag;
+    if (want >= 0) {
+      const int slot = (int)(want % kRing);
+      HIP_TRY(hipEventSynchronize(p->ring_ev[slot]));
+      if (all_stopped(p->h_ring + (size_t)slot * p->P.B, p->P.B)) break;
+    }
+  }
+  return abac_minres_finish(p, iters, relres, status);
+}
+
+abac_status abac_profile_enable(abac_plan* p, int on) {
+  if (!p) return fail(ABAC_EINVAL, "NULL plan");
+  p->prof = on != 0;
+  return ABAC_OK;
+}
+
+abac_status abac_profile_read(abac_plan* p, int kernel, double* total_ms, long long* launches) {
+  if (!p || kernel < 0 || kernel >= ABAC_K_COUNT) return fail(ABAC_EINVAL, "bad argument");
+  abac_status s = flush_prof(p);
+  if (s != ABAC_OK) return s;
+  if (total_ms) *total_ms = p->prof_ms[kernel];
+  if (launches) *launches = p->prof_n[kernel];
+  return ABAC_OK;
+}
+
+abac_status abac_profile_reset(abac_plan* p) {
+  if (!p) return fail(ABAC_EINVAL, "NULL plan");
+  abac_status s = flush_prof(p);
+  if (s != ABAC_OK) return s;
+  for (int k = 0; k < ABAC_K_COUNT; ++k) {
+    p->prof_ms[k] = 0;
+    p->prof_n[k] = 0;
+  }
+  return ABAC_OK;
+}
+
+const char* abac_status_string(int s) {
+  switch (s) {
+    case ABAC_OK: return "ok";
+    case ABAC_EINVAL: return "invalid argument";
+    case ABAC_ENOMEM: return "out of memory";
+    case ABAC_EDEVICE: return "device error";
+    case ABAC_ENOTCONV: return "not converged";
+    case ABAC_EBREAKDOWN: return "breakdown";
+    case ABAC_EBUDGET: return "over budget";
+    case ABAC_EAGAIN: return "not ready";
+    default: return "unknown status";
+  }
+}
+
+const char* abac_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,270 @@
+// Stencil and vector kernels of the ABAC MINRES path:
+//   * Y T x matvec (eqs. (1.2), (1.4)) as an HBM sweep that marches over time levels
+//     from both ends at once, so that <Y T z, z> pairs level k of T z with level
+//     nt-1-k of z without a second read of z;
+//   * the explicit residual ||f - T u|| used to confirm convergence;
+//   * right-hand side assembly of eq. (1.2);
+//   * solve set-up and the MINRES w / x / r update with its residual norm.
+#include "abac_internal.h"
+
+namespace abac {
+
+namespace {
+
+constexpr int kStencilThreads = 256;
+constexpr int kChunk = 32;          // forward time levels per block (plus the mirrored ones)
+constexpr int kVecThreads = 256;
+constexpr int kVecPerThread = 4;
+
+// (L s)_i at spatial point (ix, iy) of one level, zero Dirichlet ghosts.
+__device__ __forceinline__ double apply_L(const DevPlan& P, const double* __restrict__ lvl, int i, int ix, int iy) {
+  const double c = lvl[i];
+  double sx = 0.0, sy = 0.0;
+  if (ix > 0) sx += lvl[i - 1];
+  if (ix < P.nx - 1) sx += lvl[i + 1];
+  if (P.ny) {
+    if (iy > 0) sy += lvl[i - P.nx];
+    if (iy < P.ny - 1) sy += lvl[i + P.nx];
+  }
+  return P.c0 * c - P.cx * sx - P.cy * sy;
+}
+
+__global__ void __launch_bounds__(kStencilThreads)
+k_stencil(DevPlan P, int mode, const double* __restrict__ xin, double* __restrict__ yout,
+          const double* __restrict__ fref) {
+  const int b = blockIdx.y;
+  MinresState* st = P.st + b;
+  const double* x = xin;
+  double* y = yout;
+  if (mode == STENCIL_MINRES || mode == STENCIL_RESIDUAL) {
+    if (st->state != ST_RUNNING) return;
+    if (mode == STENCIL_RESIDUAL && !st->need_check) return;
+    if (mode == STENCIL_MINRES) {
+      const int j = st->iter + 1;
+      x = P.Z[j & 1];
+      y = P.V[(j + 1) % 3];
+    }
+  }
+  x += (size_t)b * P.N;
+  if (y) y += (size_t)b * P.N;
+  const double* f = fref ? fref + (size_t)b * P.N : nullptr;
+
+  const int n = P.nt, m = P.m;
+  const int tiles = (m + kStencilThreads - 1) / kStencilThreads;
+  const int nchunks = (n / 2 + kChunk - 1) / kChunk;
+  const int nblk = tiles * nchunks;
+  const int lb = xcd_remap(blockIdx.x, nblk);
+  const int tile = lb % tiles, chunk = lb / tiles;
+  const int i = tile * kStencilThreads + threadIdx.x;
+  const bool act = i < m;
+  const int ix = act ? i % P.nx : 0, iy = act ? i / P.nx : 0;
+  const int k0 = chunk * kChunk;
+  const int k1 = min(k0 + kChunk, n / 2);
+
+  double acc = 0.0;
+  if (act) {
+    // forward march state: x_{k-1}, x_{k-2} and L of them
+    double zf1 = 0.0, zf2 = 0.0, Lf1 = 0.0, Lf2 = 0.0;
+    if (k0 >= 2) { zf2 = x[(size_t)(k0 - 2) * m + i]; Lf2 = apply_L(P, x + (size_t)(k0 - 2) * m, i, ix, iy); }
+    if (k0 >= 1) { zf1 = x[(size_t)(k0 - 1) * m + i]; Lf1 = apply_L(P, x + (size_t)(k0 - 1) * m, i, ix, iy); }
+    // backward march state at kb = n-1-k0: x_kb, x_{kb-1} and L of them
+    const int kb0 = n - 1 - k0;
+    double zb0 = x[(size_t)kb0 * m + i], Lb0 = apply_L(P, x + (size_t)kb0 * m, i, ix, iy);
+    double zb1 = x[(size_t)(kb0 - 1) * m + i], Lb1 = apply_L(P, x + (size_t)(kb0 - 1) * m, i, ix, iy);
+    for (int k = k0; k < k1; ++k) {
+      const double* lk = x + (size_t)k * m;
+      const double zk = lk[i];
+      const double Lk = apply_L(P, lk, i, ix, iy);
+      const double out_f = Lk + Lf2 - 2.0 * zf1;          // (T x)_k
+      const int kb = n - 1 - k;
+      const double* lb2 = x + (size_t)(kb - 2) * m;
+      const double zb2 = lb2[i];
+      const double Lb2 = apply_L(P, lb2, i, ix, iy);
+      const double out_b = Lb0 + Lb2 - 2.0 * zb1;         // (T x)_kb
+      if (mode >= STENCIL_RESIDUAL) {
+        const double rf = f[(size_t)k * m + i] - out_f;
+        const double rb = f[(size_t)kb * m + i] - out_b;
+        acc += rf * rf + rb * rb;
+      } else {
+        y[(size_t)(n - 1 - k) * m + i] = out_f;           // Y reverses time
+        y[(size_t)(n - 1 - kb) * m + i] = out_b;
+        if (mode == STENCIL_MINRES) acc += out_f * zb0 + out_b * zk;
+      }
+      zf2 = zf1; Lf2 = Lf1; zf1 = zk; Lf1 = Lk;
+      zb0 = zb1; Lb0 = Lb1; zb1 = zb2; Lb1 = Lb2;
+    }
+  }
+  if (mode == STENCIL_PLAIN) return;
+  const double bs = block_sum(acc);
+  if (!arrive_last(P, b, blockIdx.x, nblk, bs)) return;
+  const double tot = finish_sum(P, b, nblk);
+  if (threadIdx.x != 0) return;
+  if (mode == STENCIL_MINRES) {
+    st->delta = tot * st->sig * st->sig;
+  } else if (mode == STENCIL_REPORT) {
+    st->res2 = tot;
+  } else {
+    st->res2 = tot;
+    if (tot <= st->tol2 * st->bnorm2) {
+      st->state = ST_DONE;
+      st->status = 0;
+    } else if (st->iter >= st->maxit) {
+      st->state = ST_DONE;
+      st->status = -4;  // ABAC_ENOTCONV
+    } else if (!(tot == tot) || tot > 1e300) {
+      st->state = ST_DONE;
+      st->status = -5;  // ABAC_EBREAKDOWN
+    } else {
+      st->explicit_mode = 1;
+    }
+    st->need_check = 0;
+  }
+}
+
+// f_1 = tau^2 src_0 / 2 + tau psi1 + psi0; f_2 = tau^2 src_1 - L psi0; f_k = tau^2 src_{k-1}
+__global__ void __launch_bounds__(kVecThreads)
+k_rhs(DevPlan P, const double* __restrict__ src, const double* __restrict__ psi0,
+      const double* __restrict__ psi1, double* __restrict__ f) {
+  const size_t total = (size_t)P.B * P.N;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t b = e / P.N;
+    const size_t r = e - b * P.N;
+    const int k = (int)(r / P.m);
+    const int i = (int)(r - (size_t)k * P.m);
+    const double s = src[e];
+    double v = P.tau2 * s;
+    if (k == 0) {
+      v = 0.5 * P.tau2 * s + P.tau * psi1[b * P.m + i] + psi0[b * P.m + i];
+    } else if (k == 1) {
+      v -= apply_L(P, psi0 + b * P.m, i, i % P.nx, i / P.nx);
+    }
+    f[e] = v;
+  }
+}
+
+// Set-up of a solve: b = Y f into R and V_1, zero V_0, W_0, W_1 and u, ||b||^2.
+__global__ void __launch_bounds__(kVecThreads)
+k_init(DevPlan P, const double* __restrict__ f, double* __restrict__ u, double tol, int maxit) {
+  const int b = blockIdx.y;
+  const size_t off = (size_t)b * P.N;
+  const int nblk = gridDim.x;
+  const size_t per = ((size_t)P.N + nblk - 1) / nblk;
+  const size_t lo = (size_t)blockIdx.x * per;
+  const size_t hi = lo + per < (size_t)P.N ? lo + per : (size_t)P.N;
+  double acc = 0.0;
+  for (size_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+    const int k = (int)(e / P.m);
+    const size_t i = e - (size_t)k * P.m;
+    const double v = f[off + (size_t)(P.nt - 1 - k) * P.m + i];
+    P.R[off + e] = v;
+    P.V[1][off + e] = v;
+    P.V[0][off + e] = 0.0;
+    P.W[0][off + e] = 0.0;
+    P.W[1][off + e] = 0.0;
+    u[off + e] = 0.0;
+    acc += v * v;
+  }
+  const double bs = block_sum(acc);
+  if (!arrive_last(P, b, blockIdx.x, nblk, bs)) return;
+  const double tot = finish_sum(P, b, nblk);
+  if (threadIdx.x != 0) return;
+  MinresState* st = P.st + b;
+  st->bnorm2 = tot;
+  st->tol2 = tol * tol;
+  st->maxit = maxit;
+  st->iter = 0;
+  st->explicit_mode = 0;
+  st->need_check = 0;
+  st->rnorm2 = tot;
+  st->res2 = tot;
+  st->status = 0;
+  if (tot == 0.0) {
+    st->state = ST_DONE;   // u = 0 is exact
+  } else if (!(tot == tot) || tot > 1e300) {
+    st->state = ST_DONE;
+    st->status = -5;
+  } else {
+    st->state = ST_RUNNING;
+  }
+}
+
+// w_j = wa Z_j - wb w_{j-1} - wc w_{j-2};  x += xc w_j;  r = r1 r + r2 V_{j+1};  ||r||^2
+__global__ void __launch_bounds__(kVecThreads)
+k_update(DevPlan P, double* __restrict__ u) {
+  const int b = blockIdx.y;
+  MinresState* st = P.st + b;
+  if (st->state != ST_RUNNING) return;
+  const int j = st->iter;
+  const double wa = st->wa, wb = st->wb, wc = st->wc, xc = st->xc, r1 = st->r1, r2 = st->r2;
+  const size_t off = (size_t)b * P.N;
+  const double* __restrict__ Zj = P.Z[j & 1] + off;
+  const double* __restrict__ Wm1 = P.W[(j - 1) & 1] + off;
+  double* __restrict__ Wm2 = P.W[j & 1] + off;
+  const double* __restrict__ Vn = P.V[(j + 1) % 3] + off;
+  double* __restrict__ R = P.R + off;
+  double* __restrict__ X = u + off;
+  const int nblk = gridDim.x;
+  const size_t per = ((size_t)P.N + nblk - 1) / nblk;
+  const size_t lo = (size_t)blockIdx.x * per;
+  const size_t hi = lo + per < (size_t)P.N ? lo + per : (size_t)P.N;
+  double acc = 0.0;
+  for (size_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+    const double w = wa * Zj[e] - wb * Wm1[e] - wc * Wm2[e];
+    Wm2[e] = w;
+    X[e] += xc * w;
+    const double r = r1 * R[e] + r2 * Vn[e];
+    R[e] = r;
+    acc += r * r;
+  }
+  const double bs = block_sum(acc);
+  if (!arrive_last(P, b, blockIdx.x, nblk, bs)) return;
+  const double tot = finish_sum(P, b, nblk);
+  if (threadIdx.x != 0) return;
+  st->rnorm2 = tot;
+  if (tot <= st->tol2 * st->bnorm2 || st->explicit_mode || st->iter >= st->maxit || st->need_check)
+    st->need_check = 1;
+}
+
+}  // namespace
+
+int stencil_blocks(const DevPlan& P) {
+  const int tiles = (P.m + kStencilThreads - 1) / kStencilThreads;
+  const int nchunks = (P.nt / 2 + kChunk - 1) / kChunk;
+  return tiles * nchunks;
+}
+
+int update_blocks(const DevPlan& P) {
+  long long want = (P.N + (long long)kVecThreads * kVecPerThread - 1) / ((long long)kVecThreads * kVecPerThread);
+  if (want > 4096) want = 4096;
+  if (want < 1) want = 1;
+  return (int)want;
+}
+
+hipError_t launch_stencil(const DevPlan& P, int mode, const double* x, double* y, const double* f, hipStream_t s) {
+  dim3 grid(stencil_blocks(P), P.B);
+  hipLaunchKernelGGL(k_stencil, grid, dim3(kStencilThreads), 0, s, P, mode, x, y, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs(const DevPlan& P, const double* src, const double* psi0, const double* psi1, double* f,
+                      hipStream_t s) {
+  long long total = (long long)P.B * P.N;
+  long long blocks = (total + kVecThreads - 1) / kVecThreads;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_rhs, dim3((unsigned)blocks), dim3(kVecThreads), 0, s, P, src, psi0, psi1, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const DevPlan& P, const double* f, double* u, double tol, int maxit, hipStream_t s) {
+  dim3 grid(update_blocks(P), P.B);
+  hipLaunchKernelGGL(k_init, grid, dim3(kVecThreads), 0, s, P, f, u, tol, maxit);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const DevPlan& P, double* u, hipStream_t s) {
+  dim3 grid(update_blocks(P), P.B);
+  hipLaunchKernelGGL(k_update, grid, dim3(kVecThreads), 0, s, P, u);
+  return hipGetLastError();
+}
+
+}  // namespace abac

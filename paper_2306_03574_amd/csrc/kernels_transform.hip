@@ -1,0 +1,559 @@
+// Transform passes of z = P_alpha^{-1} r (Section 2.3), computed as
+//     z = S [ K Y K Y ] S r,   K = D^{-1} F^{-1} diag(mu^{-1/2}) F D  (per spatial mode),
+// where S is the orthonormal DST-I in space (S = S^T = S^{-1}, so the inner DST pair
+// of the three-step recipe done twice cancels), F the DFT over the nt time levels,
+// D = diag(a^t), a = alpha^{1/nt}, Y the time reversal, and mu the eigenvalues of
+// C_alpha (eq. (1.7), Appendix A).  The transposed factor uses
+// (C^{-1/2})^T = Y C^{-1/2} Y (Lemma on the realness and symmetry of C_alpha^{1/2},
+// Section 2.1).
+//
+// DST-I of length M-1 is taken from a complex FFT of length 2M of the odd extension;
+// two real rows ride in one complex sequence (real and imaginary part).  The time
+// FFTs are real transforms of two spatial modes packed the same way; the per-mode
+// spectral weights are applied to the packed spectrum in closed form.
+//
+// Scratch layout (private to the apply): [batch][nt][ny1][Mx] in the transform
+// precision, Mx = nx+1; column Mx-1 is a zero pad so rows and mode pairs are aligned.
+#include "abac_internal.h"
+
+namespace abac {
+
+namespace {
+
+template <int L> constexpr int seqs_per_block() { return fft_tps<L>() >= 256 ? 1 : 256 / fft_tps<L>(); }
+template <int L> constexpr int block_threads() { return seqs_per_block<L>() * fft_tps<L>(); }
+
+template <typename T>
+__device__ __forceinline__ cplx<T> inv_sqrt_principal(cplx<T> mu) {
+  // 1/s(mu), s the principal square root: s(mu) = (w, y/(2w)) for x >= 0 and
+  // (|y|/(2w), sign(y) w) for x < 0 with w = sqrt((|mu| + |x|)/2); 1/s = conj(s)/|mu|.
+  const T x = mu.x, y = mu.y;
+  const T r = sqrt(x * x + y * y);
+  const T w = sqrt((r + fabs(x)) * (T)0.5);
+  T sr, si;
+  if (x >= (T)0) {
+    sr = w;
+    si = y / (w + w);
+  } else {
+    sr = fabs(y) / (w + w);
+    si = copysign(w, y);
+  }
+  const T ir = (T)1 / r;
+  return cplx<T>{sr * ir, -si * ir};
+}
+
+__device__ __forceinline__ void finalize_gamma_init(MinresState* st, double g2) {
+  if (!(g2 > 0.0) || !(g2 < 1e300)) {
+    st->state = ST_DONE;
+    st->status = -5;  // ABAC_EBREAKDOWN
+    return;
+  }
+  const double g = sqrt(g2);
+  st->gamma = g;
+  st->sig = 1.0 / g;
+  st->sig_prev = 0.0;
+  st->eta = g;
+  st->c1 = 1.0; st->c2 = 1.0;
+  st->s1 = 0.0; st->s2 = 0.0;
+  st->iter = 0;
+}
+
+// Lanczos coefficient gamma_{j+1} and the Givens QR update of iteration j.
+__device__ __forceinline__ void finalize_gamma_iter(MinresState* st, double g2) {
+  if (!(g2 >= 0.0) || !(g2 < 1e300)) {
+    st->state = ST_DONE;
+    st->status = -5;
+    st->iter += 1;
+    return;
+  }
+  const double gn = sqrt(g2);
+  const double gam = st->gamma, del = st->delta;
+  const double eps = st->s2 * gam;
+  const double dbar = st->c2 * gam;
+  const double dp = st->c1 * dbar + st->s1 * del;
+  const double t2 = -st->s1 * dbar + st->c1 * del;
+  const double rho = hypot(t2, gn);
+  if (!(rho > 0.0) || !(rho < 1e300)) {
+    st->state = ST_DONE;
+    st->status = -5;
+    st->iter += 1;
+    return;
+  }
+  const double c = t2 / rho, s = gn / rho;
+  st->wa = st->sig / rho;
+  st->wb = dp / rho;
+  st->wc = eps / rho;
+  st->xc = c * st->eta;
+  st->r1 = s * s;
+  st->r2 = gn > 0.0 ? -s * c * st->eta / gn : 0.0;
+  st->eta = -s * st->eta;
+  st->c2 = st->c1; st->c1 = c;
+  st->s2 = st->s1; st->s1 = s;
+  st->sig_prev = st->sig;
+  st->sig = gn > 0.0 ? 1.0 / gn : 0.0;
+  st->gamma = gn;
+  st->iter += 1;
+  if (gn == 0.0) st->need_check = 1;
+}
+
+// ---------------------------------------------------------------------------
+// first pass: DST-I along x of every row (FP64 in, transform precision out),
+// optionally fused with the Lanczos step q = sig_j A Z_j - delta v_j - gamma_j v_{j-1}
+// ---------------------------------------------------------------------------
+template <typename T, int L>
+__global__ void __launch_bounds__(block_threads<L>())
+k_dstx_fwd(DevPlan P, int mode, int check, const double* __restrict__ in) {
+  using C = cplx<T>;
+  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_per_block<L>(), Mx = L / 2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  T* stage = reinterpret_cast<T*>(smem);
+  const int b = blockIdx.y;
+  const size_t off = (size_t)b * P.N;
+  const double* src = in ? in + off : nullptr;
+  double* qout = nullptr;
+  const double* vj = nullptr;
+  const double* vjm1 = nullptr;
+  double cA = 1.0, cB = 0.0, cC = 0.0;
+  if (check || mode == FWD_LANCZOS) {
+    const MinresState* st = P.st + b;
+    if (st->state != ST_RUNNING) return;
+    if (mode == FWD_LANCZOS) {
+      const int j = st->iter + 1;
+      qout = P.V[(j + 1) % 3] + off;
+      src = qout;
+      vj = P.V[j % 3] + off;
+      vjm1 = P.V[(j + 2) % 3] + off;
+      cA = st->sig;
+      cB = st->delta * st->sig;
+      cC = st->gamma * st->sig_prev;
+    }
+  }
+  const int nx = P.nx;
+  const int rows = P.nt * P.ny1;
+  const int row0 = blockIdx.x * 2 * S;
+  const int nrows = min(2 * S, rows - row0);
+  const size_t base = (size_t)row0 * nx;
+  const int cnt = nrows * nx;
+  if (mode == FWD_LANCZOS) {
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+      const double q = cA * src[base + e] - cB * vj[base + e] - cC * vjm1[base + e];
+      qout[base + e] = q;
+      stage[e] = (T)q;
+    }
+  } else {
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) stage[e] = (T)src[base + e];
+  }
+  __syncthreads();
+  const int s = threadIdx.x % S, j = threadIdx.x / S;
+  const int ra = 2 * s, rb = 2 * s + 1;
+  const bool va = ra < nrows, vb = rb < nrows;
+  C v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int t = j + i * TPS;
+    T a = 0, c = 0;
+    if (t > 0 && t < Mx) {
+      if (va) a = stage[ra * nx + t - 1];
+      if (vb) c = stage[rb * nx + t - 1];
+    } else if (t > Mx) {
+      const int idx = 2 * Mx - t - 1;
+      if (va) a = -stage[ra * nx + idx];
+      if (vb) c = -stage[rb * nx + idx];
+    }
+    v[i] = C{a, c};
+  }
+  __syncthreads();
+  fft_seq<T, L, false>(v, j, lds + s, S, reinterpret_cast<const C*>(P.twx));
+  const T scl = (T)(1.0 / sqrt((double)L));
+  T* out = reinterpret_cast<T*>(P.scratch) + (size_t)b * P.NS;
+#pragma unroll
+  for (int i = 0; i <= R / 2; ++i) {
+    const int k = j + i * TPS;
+    if (k == 0 || k > Mx) continue;
+    int col;
+    T oa, ob;
+    if (k == Mx) {
+      col = Mx - 1; oa = 0; ob = 0;
+    } else {
+      col = k - 1; oa = -v[i].y * scl; ob = v[i].x * scl;
+    }
+    if (va) out[(size_t)(row0 + ra) * Mx + col] = oa;
+    if (vb) out[(size_t)(row0 + rb) * Mx + col] = ob;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y pass (2D): DST-I along y of every column, in place on the scratch; two adjacent
+// columns form one complex sequence.
+// ---------------------------------------------------------------------------
+template <typename T, int L>
+__global__ void __launch_bounds__(block_threads<L>())
+k_dsty(DevPlan P, int check) {
+  using C = cplx<T>;
+  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_per_block<L>(), My = L / 2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  const int b = blockIdx.y;
+  if (check && P.st[b].state != ST_RUNNING) return;
+  const int cpairs = P.Mx / 2;
+  const int bpl = (cpairs + S - 1) / S;
+  const int t = blockIdx.x / bpl, cb = blockIdx.x % bpl;
+  const int s = threadIdx.x % S, j = threadIdx.x / S;
+  const int cp = cb * S + s;
+  const bool valid = cp < cpairs;
+  const int ld = P.Mx / 2;
+  C* col = reinterpret_cast<C*>(reinterpret_cast<T*>(P.scratch) + (size_t)b * P.NS + (size_t)t * P.ms) + cp;
+  C v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int tt = j + i * TPS;
+    C z{0, 0};
+    if (valid) {
+      if (tt > 0 && tt < My) {
+        z = col[(size_t)(tt - 1) * ld];
+      } else if (tt > My) {
+        const C w = col[(size_t)(2 * My - tt - 1) * ld];
+        z = C{-w.x, -w.y};
+      }
+    }
+    v[i] = z;
+  }
+  fft_seq<T, L, false>(v, j, lds + s, S, reinterpret_cast<const C*>(P.twy));
+  const T scl = (T)(1.0 / sqrt((double)L));
+  if (!valid) return;
+#pragma unroll
+  for (int i = 0; i <= R / 2; ++i) {
+    const int k = j + i * TPS;
+    if (k == 0 || k >= My) continue;
+    col[(size_t)(k - 1) * ld] = C{-v[i].y * scl, v[i].x * scl};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// time pass: per spatial mode pair, out = K Y K Y g, in place on the scratch.
+// ---------------------------------------------------------------------------
+template <typename T, int NT>
+__global__ void __launch_bounds__(block_threads<NT>())
+k_time(DevPlan P, int check) {
+  using C = cplx<T>;
+  constexpr int R = FftShape<NT>::R, TPS = NT / R, S = seqs_per_block<NT>();
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  const int b = blockIdx.y;
+  if (check && P.st[b].state != ST_RUNNING) return;
+  const int s = threadIdx.x % S, j = threadIdx.x / S;
+  const int npairs = P.ms / 2;
+  const int pair = blockIdx.x * S + s;
+  const bool valid = pair < npairs;
+  const int ld = npairs;
+  C* g = reinterpret_cast<C*>(reinterpret_cast<T*>(P.scratch) + (size_t)b * P.NS) + pair;
+  const T* __restrict__ sc = reinterpret_cast<const T*>(P.sc);
+  const T* __restrict__ sci = reinterpret_cast<const T*>(P.sci);
+  const C* __restrict__ abk = reinterpret_cast<const C*>(P.abk);
+  const C* __restrict__ tw = reinterpret_cast<const C*>(P.twt);
+  const T* __restrict__ beta = reinterpret_cast<const T*>(P.beta);
+  const T ba = valid ? beta[2 * pair] : (T)0;
+  const T bb = valid ? beta[2 * pair + 1] : (T)0;
+  C* my = lds + s;
+  C v[R];
+  // Y then D: e_t = a^t g_{nt-1-t}
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int t = j + i * TPS;
+    const C z = valid ? g[(size_t)(NT - 1 - t) * ld] : C{0, 0};
+    v[i] = cscale(z, sc[t]);
+  }
+  const T half_inv_n = (T)(0.5 / NT);
+#pragma unroll 1
+  for (int rep = 0; rep < 2; ++rep) {
+    fft_seq<T, NT, false>(v, j, my, S, tw);
+    // packed spectrum Z_k of the two modes; apply mu^{-1/2} per mode:
+    // Z'_k = ((Ma + Mb) Z_k + (Ma - Mb) conj(Z_{nt-k})) / 2, with the 1/nt of F^{-1}
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R; ++i) my[(j + i * TPS) * S] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int k = j + i * TPS;
+      const int kp = (NT - k) & (NT - 1);
+      const C zp = cconj(my[kp * S]);
+      const C A = abk[2 * k], Bk = abk[2 * k + 1];
+      const C Ma = inv_sqrt_principal<T>(C{A.x + ba * Bk.x, A.y + ba * Bk.y});
+      const C Mb = inv_sqrt_principal<T>(C{A.x + bb * Bk.x, A.y + bb * Bk.y});
+      const C o = cadd(cmul(cadd(Ma, Mb), v[i]), cmul(csub(Ma, Mb), zp));
+      v[i] = cscale(o, half_inv_n);
+    }
+    __syncthreads();
+    fft_seq<T, NT, true>(v, j, my, S, tw);
+    if (rep == 0) {
+      // D^{-1}, then Y, then D:  h_t = a^{2t-nt+1} c_{nt-1-t}
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < R; ++i) my[(j + i * TPS) * S] = v[i];
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int t = j + i * TPS;
+        v[i] = cscale(my[(NT - 1 - t) * S], sc[t] * sci[NT - 1 - t]);
+      }
+      __syncthreads();
+    }
+  }
+  if (!valid) return;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int t = j + i * TPS;
+    g[(size_t)t * ld] = cscale(v[i], sci[t]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// last pass: inverse DST-I along x (transform precision in, FP64 out), optionally
+// fused with <q, p> and the MINRES scalar update.
+// ---------------------------------------------------------------------------
+template <typename T, int L>
+__global__ void __launch_bounds__(block_threads<L>())
+k_dstx_inv(DevPlan P, int mode, double* __restrict__ outp) {
+  using C = cplx<T>;
+  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_per_block<L>(), Mx = L / 2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  T* stage = reinterpret_cast<T*>(smem);
+  const int b = blockIdx.y;
+  const size_t off = (size_t)b * P.N;
+  double* out = outp ? outp + off : nullptr;
+  const double* q = nullptr;
+  MinresState* st = P.st + b;
+  if (mode != INV_PLAIN) {
+    if (st->state != ST_RUNNING) return;
+    if (mode == INV_GAMMA_INIT) {
+      out = P.Z[1] + off;
+      q = P.V[1] + off;
+    } else {
+      const int jj = st->iter + 1;
+      out = P.Z[(jj + 1) & 1] + off;
+      q = P.V[(jj + 1) % 3] + off;
+    }
+  }
+  const int nx = P.nx;
+  const int rows = P.nt * P.ny1;
+  const int row0 = blockIdx.x * 2 * S;
+  const int nrows = min(2 * S, rows - row0);
+  const T* scr = reinterpret_cast<const T*>(P.scratch) + (size_t)b * P.NS + (size_t)row0 * Mx;
+  const int cnt = nrows * Mx;
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) stage[e] = scr[e];
+  __syncthreads();
+  const int s = threadIdx.x % S, j = threadIdx.x / S;
+  const int ra = 2 * s, rb = 2 * s + 1;
+  const bool va = ra < nrows, vb = rb < nrows;
+  C v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int t = j + i * TPS;
+    T a = 0, c = 0;
+    if (t > 0 && t < Mx) {
+      if (va) a = stage[ra * Mx + t - 1];
+      if (vb) c = stage[rb * Mx + t - 1];
+    } else if (t > Mx) {
+      const int idx = 2 * Mx - t - 1;
+      if (va) a = -stage[ra * Mx + idx];
+      if (vb) c = -stage[rb * Mx + idx];
+    }
+    v[i] = C{a, c};
+  }
+  __syncthreads();
+  fft_seq<T, L, false>(v, j, lds + s, S, reinterpret_cast<const C*>(P.twx));
+  const double scl = 1.0 / sqrt((double)L);
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i <= R / 2; ++i) {
+    const int k = j + i * TPS;
+    if (k == 0 || k >= Mx) continue;
+    const double pa = -(double)v[i].y * scl, pb = (double)v[i].x * scl;
+    const size_t ia = (size_t)(row0 + ra) * nx + (k - 1);
+    const size_t ib = (size_t)(row0 + rb) * nx + (k - 1);
+    if (va) {
+      out[ia] = pa;
+      if (q) acc += pa * q[ia];
+    }
+    if (vb) {
+      out[ib] = pb;
+      if (q) acc += pb * q[ib];
+    }
+  }
+  if (mode == INV_PLAIN) return;
+  const double bs = block_sum(acc);
+  const int nblk = gridDim.x;
+  if (!arrive_last(P, b, blockIdx.x, nblk, bs)) return;
+  const double tot = finish_sum(P, b, nblk);
+  if (threadIdx.x != 0) return;
+  if (mode == INV_GAMMA_INIT) finalize_gamma_init(st, tot);
+  else finalize_gamma_iter(st, tot);
+}
+
+template <typename T, int L>
+hipError_t launch_x_fwd_t(const DevPlan& P, int mode, int check, const double* in, hipStream_t s) {
+  constexpr int S = seqs_per_block<L>();
+  const int rows = P.nt * P.ny1;
+  dim3 grid((rows + 2 * S - 1) / (2 * S), P.B);
+  const size_t lds = (size_t)S * L * sizeof(cplx<T>);
+  hipLaunchKernelGGL((k_dstx_fwd<T, L>), grid, dim3(block_threads<L>()), lds, s, P, mode, check, in);
+  return hipGetLastError();
+}
+
+template <typename T, int L>
+hipError_t launch_x_inv_t(const DevPlan& P, int mode, double* out, hipStream_t s) {
+  constexpr int S = seqs_per_block<L>();
+  const int rows = P.nt * P.ny1;
+  dim3 grid((rows + 2 * S - 1) / (2 * S), P.B);
+  const size_t lds = (size_t)S * L * sizeof(cplx<T>);
+  hipLaunchKernelGGL((k_dstx_inv<T, L>), grid, dim3(block_threads<L>()), lds, s, P, mode, out);
+  return hipGetLastError();
+}
+
+template <typename T, int L>
+hipError_t launch_y_t(const DevPlan& P, int check, hipStream_t s) {
+  constexpr int S = seqs_per_block<L>();
+  const int cpairs = P.Mx / 2;
+  const int bpl = (cpairs + S - 1) / S;
+  dim3 grid(bpl * P.nt, P.B);
+  const size_t lds = (size_t)S * L * sizeof(cplx<T>);
+  hipLaunchKernelGGL((k_dsty<T, L>), grid, dim3(block_threads<L>()), lds, s, P, check);
+  return hipGetLastError();
+}
+
+template <typename T, int NT>
+hipError_t launch_time_t(const DevPlan& P, int check, hipStream_t s) {
+  constexpr int S = seqs_per_block<NT>();
+  const int npairs = P.ms / 2;
+  dim3 grid((npairs + S - 1) / S, P.B);
+  const size_t lds = (size_t)S * NT * sizeof(cplx<T>);
+  hipLaunchKernelGGL((k_time<T, NT>), grid, dim3(block_threads<NT>()), lds, s, P, check);
+  return hipGetLastError();
+}
+
+#define ABAC_SWITCH_L(LVAR, CALL)                      \
+  switch (LVAR) {                                      \
+    case 16: return CALL(16);                          \
+    case 32: return CALL(32);                          \
+    case 64: return CALL(64);                          \
+    case 128: return CALL(128);                        \
+    case 256: return CALL(256);                        \
+    case 512: return CALL(512);                        \
+    case 1024: return CALL(1024);                      \
+    case 2048: return CALL(2048);                      \
+    case 4096: return CALL(4096);                      \
+    case 8192: return CALL(8192);                      \
+    default: return hipErrorInvalidValue;              \
+  }
+
+#define ABAC_SWITCH_NT(LVAR, CALL)                     \
+  switch (LVAR) {                                      \
+    case 8: return CALL(8);                            \
+    case 16: return CALL(16);                          \
+    case 32: return CALL(32);                          \
+    case 64: return CALL(64);                          \
+    case 128: return CALL(128);                        \
+    case 256: return CALL(256);                        \
+    case 512: return CALL(512);                        \
+    case 1024: return CALL(1024);                      \
+    default: return hipErrorInvalidValue;              \
+  }
+
+template <typename T>
+hipError_t x_fwd_dispatch(const DevPlan& P, int mode, int check, const double* in, hipStream_t s) {
+#define CALL(LL) launch_x_fwd_t<T, LL>(P, mode, check, in, s)
+  ABAC_SWITCH_L(2 * P.Mx, CALL)
+#undef CALL
+}
+
+template <typename T>
+hipError_t x_inv_dispatch(const DevPlan& P, int mode, double* out, hipStream_t s) {
+#define CALL(LL) launch_x_inv_t<T, LL>(P, mode, out, s)
+  ABAC_SWITCH_L(2 * P.Mx, CALL)
+#undef CALL
+}
+
+template <typename T>
+hipError_t y_dispatch(const DevPlan& P, int check, hipStream_t s) {
+#define CALL(LL) launch_y_t<T, LL>(P, check, s)
+  switch (2 * P.My) {
+    case 16: return CALL(16);
+    case 32: return CALL(32);
+    case 64: return CALL(64);
+    case 128: return CALL(128);
+    case 256: return CALL(256);
+    case 512: return CALL(512);
+    case 1024: return CALL(1024);
+    default: return hipErrorInvalidValue;
+  }
+#undef CALL
+}
+
+template <typename T>
+hipError_t time_dispatch(const DevPlan& P, int check, hipStream_t s) {
+#define CALL(LL) launch_time_t<T, LL>(P, check, s)
+  ABAC_SWITCH_NT(P.nt, CALL)
+#undef CALL
+}
+
+}  // namespace
+
+hipError_t launch_dstx_fwd(const DevPlan& P, int prec, int mode, int check, const double* in, hipStream_t s) {
+  return prec ? x_fwd_dispatch<float>(P, mode, check, in, s) : x_fwd_dispatch<double>(P, mode, check, in, s);
+}
+
+hipError_t launch_dsty(const DevPlan& P, int prec, int check, hipStream_t s) {
+  return prec ? y_dispatch<float>(P, check, s) : y_dispatch<double>(P, check, s);
+}
+
+hipError_t launch_time(const DevPlan& P, int prec, int check, hipStream_t s) {
+  return prec ? time_dispatch<float>(P, check, s) : time_dispatch<double>(P, check, s);
+}
+
+hipError_t launch_dstx_inv(const DevPlan& P, int prec, int mode, double* out, hipStream_t s) {
+  return prec ? x_inv_dispatch<float>(P, mode, out, s) : x_inv_dispatch<double>(P, mode, out, s);
+}
+
+int dstx_blocks(const DevPlan& P, int prec) {
+  (void)prec;
+  int S;
+  switch (2 * P.Mx) {
+    case 16: S = seqs_per_block<16>(); break;
+    case 32: S = seqs_per_block<32>(); break;
+    case 64: S = seqs_per_block<64>(); break;
+    case 128: S = seqs_per_block<128>(); break;
+    case 256: S = seqs_per_block<256>(); break;
+    case 512: S = seqs_per_block<512>(); break;
+    case 1024: S = seqs_per_block<1024>(); break;
+    case 2048: S = seqs_per_block<2048>(); break;
+    case 4096: S = seqs_per_block<4096>(); break;
+    default: S = seqs_per_block<8192>(); break;
+  }
+  const int rows = P.nt * P.ny1;
+  return (rows + 2 * S - 1) / (2 * S);
+}
+
+size_t transform_lds_bytes(int L, int prec) {
+  const size_t c = prec ? sizeof(float2) : sizeof(double2);
+  int S;
+  switch (L) {
+    case 8: S = seqs_per_block<8>(); break;
+    case 16: S = seqs_per_block<16>(); break;
+    case 32: S = seqs_per_block<32>(); break;
+    case 64: S = seqs_per_block<64>(); break;
+    case 128: S = seqs_per_block<128>(); break;
+    case 256: S = seqs_per_block<256>(); break;
+    case 512: S = seqs_per_block<512>(); break;
+    case 1024: S = seqs_per_block<1024>(); break;
+    case 2048: S = seqs_per_block<2048>(); break;
+    case 4096: S = seqs_per_block<4096>(); break;
+    case 8192: S = seqs_per_block<8192>(); break;
+    default: return 0;
+  }
+  return (size_t)S * L * c;
+}
+
+}  // namespace abac

@@ -1,0 +1,226 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances: FP64 path <= 1e-10 relative (the bar for solutions; operators are held
+tighter), FP32-preconditioner path: converged to the same tol with at most 2 extra
+iterations.  Every case prints its identity before touching the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.discretization import Grid, L_matrix
+from oracle import allatonce as aao
+from oracle import preconditioner as pc
+from oracle import minres as mr
+from oracle import examples as ex
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _plan(nx, ny, nt, alpha=1e-3, prec="fp64", batch=1, T=1.0):
+    from paper_2306_03574_amd import Plan
+    print(f"[case] nx={nx} ny={ny} nt={nt} alpha={alpha} prec={prec} batch={batch} T={T}", flush=True)
+    return Plan(nx, ny, nt, T=T, alpha=alpha, prec=prec, batch=batch, device=DEV)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+SHAPES = [
+    (7, 0, 8), (15, 0, 16), (63, 0, 64), (255, 0, 32), (1023, 0, 8),
+    (7, 7, 8), (15, 7, 16), (7, 31, 8), (31, 31, 32), (63, 63, 16), (127, 15, 8), (255, 7, 8),
+]
+
+
+@pytest.mark.parametrize("nx,ny,nt", SHAPES)
+def test_apply_A(nx, ny, nt):
+    g = Grid(nx, ny, nt, T=1.0)
+    x = np.random.default_rng(11).standard_normal(g.shape)
+    p = _plan(nx, ny, nt)
+    y = _host(p.apply_A(_dev(x[None])))[0]
+    ref = aao.apply_A(g, x)
+    assert _rel(y, ref) < 1e-14
+
+
+@pytest.mark.parametrize("nx,ny,nt", SHAPES)
+@pytest.mark.parametrize("alpha", [1e-1, 1e-3])
+def test_apply_Pinv_fp64(nx, ny, nt, alpha):
+    g = Grid(nx, ny, nt, T=1.0)
+    r = np.random.default_rng(12).standard_normal(g.shape)
+    p = _plan(nx, ny, nt, alpha=alpha)
+    z = _host(p.apply_Pinv(_dev(r[None])))[0]
+    ref = pc.apply_Pinv(g, alpha, r)
+    assert _rel(z, ref) < 1e-11
+
+
+@pytest.mark.parametrize("nx,ny,nt", [(15, 0, 16), (63, 0, 64), (31, 31, 32), (15, 7, 16)])
+@pytest.mark.parametrize("alpha", [1e-1, 1e-2, 1e-3])
+def test_apply_Pinv_fp32(nx, ny, nt, alpha):
+    """FP32 transforms: error ~ eps32 / alpha (the D_alpha^{-1} amplification)."""
+    g = Grid(nx, ny, nt, T=1.0)
+    r = np.random.default_rng(13).standard_normal(g.shape)
+    p = _plan(nx, ny, nt, alpha=alpha, prec="fp32")
+    z = _host(p.apply_Pinv(_dev(r[None])))[0]
+    ref = pc.apply_Pinv(g, alpha, r)
+    assert _rel(z, ref) < 50 * 6e-8 / alpha
+
+
+def test_apply_Pinv_alpha_one_matches_dense():
+    """alpha = 1 (absolute-value block circulant) against the dense polar factor."""
+    nx, nt = 7, 8
+    g = Grid(nx, 0, nt)
+    r = np.random.default_rng(14).standard_normal(g.shape)
+    p = _plan(nx, 0, nt, alpha=1.0)
+    z = _host(p.apply_Pinv(_dev(r[None])))[0]
+    ref = pc.dense_apply_Pinv(g, 1.0, r)
+    assert _rel(z, ref) < 1e-11
+
+
+@pytest.mark.parametrize("nx,ny,nt", [(15, 0, 16), (15, 15, 16), (63, 0, 64)])
+def test_build_rhs(nx, ny, nt):
+    g = Grid(nx, ny, nt, T=0.8)
+    rng = np.random.default_rng(15)
+    src = rng.standard_normal(g.shape)
+    psi0 = rng.standard_normal(g.level_shape)
+    psi1 = rng.standard_normal(g.level_shape)
+    p = _plan(nx, ny, nt, T=0.8)
+    f = _host(p.build_rhs(_dev(src[None]), _dev(psi0[None]), _dev(psi1[None])))[0]
+    ref = aao.build_rhs(g, src, psi0, psi1)
+    assert _rel(f, ref) < 1e-14
+
+
+@pytest.mark.parametrize("nx,ny,nt,alpha,k", [(15, 0, 16, 1e-2, 3), (31, 31, 32, 1e-3, 4), (63, 0, 64, 1e-1, 6),
+                                              (15, 7, 16, 1e-3, 5)])
+def test_fixed_iterates(nx, ny, nt, alpha, k):
+    """u after exactly k iterations (maxit = k, unreachable tol) equals the oracle's x_k."""
+    g = Grid(nx, ny, nt)
+    src, psi0, psi1 = synth.random_source(nx, ny, nt, seed=21)
+    f = aao.build_rhs(g, src, psi0, psi1)
+    L = L_matrix(g)
+    ref = mr.minres(lambda u: aao.apply_A(g, u, L), lambda y: pc.apply_Pinv(g, alpha, y),
+                    aao.reverse_time(f), fixed_iters=k)
+    p = _plan(nx, ny, nt, alpha=alpha)
+    u, iters, relres, status = p.solve(_dev(f[None]), tol=1e-30, maxit=k)
+    assert iters == [k] and status == [-4]
+    assert _rel(_host(u)[0], ref.x) < 1e-10
+    assert abs(relres[0] - ref.relres) < 1e-8 * max(ref.relres, 1e-3)
+
+
+@pytest.mark.parametrize("alpha", [1e-1, 1e-2, 1e-3])
+def test_solve_wave1d_63x64(alpha):
+    """1D workload (nx=63, nt=64, manufactured solution + N(0, 0.1^2) noise): iteration
+    count equal to the oracle's, relres <= 1e-8, solution within 1e-10."""
+    nx, nt = 63, 64
+    g = Grid(nx, 0, nt)
+    src, psi0, psi1, _ = synth.manufactured_1d(nx, nt, noise_std=0.1, seed=1)
+    f = aao.build_rhs(g, src, psi0, psi1)
+    L = L_matrix(g)
+    ref = mr.minres(lambda u: aao.apply_A(g, u, L), lambda y: pc.apply_Pinv(g, alpha, y), aao.reverse_time(f),
+                    tol=1e-8, maxit=300)
+    p = _plan(nx, 0, nt, alpha=alpha)
+    u, iters, relres, status = p.solve(_dev(f[None]), tol=1e-8, maxit=300)
+    assert status == [0]
+    assert iters[0] == ref.iters
+    assert relres[0] <= 1e-8
+    assert _rel(_host(u)[0], ref.x) < 1e-10
+
+
+@pytest.mark.parametrize("lt,lh", [(4, 4), (5, 4), (4, 5), (6, 5)])
+def test_table1_example1_on_gpu(lt, lh):
+    """Example 1 of Section 3 at alpha = 1e-6, tol 1e-6: 2 iterations (Table 1) and the
+    printed error of the iterate (Table 2)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "section3_tables.json")))
+    e_want = {(r[0], r[1]): r[2] for r in gold["table2"]["rows"]}[(lt, lh)]
+    nt, n = 2 ** lt, 2 ** lh - 1
+    g = Grid(n, n, nt)
+    src, psi0, psi1, exact = ex.example1_data(g)
+    p = _plan(n, n, nt, alpha=1e-6)
+    f = p.build_rhs(_dev(src[None]), _dev(psi0[None]), _dev(psi1[None]))
+    u, iters, relres, status = p.solve(f, tol=1e-6, maxit=50)
+    assert status == [0] and iters == [2]
+    e = ex.error_E(g, _host(u)[0], exact)
+    assert abs(e - e_want) <= 0.006 * e_want
+
+
+@pytest.mark.parametrize("nx,ny,nt,alpha", [(63, 0, 64, 1e-2), (31, 31, 32, 1e-3), (255, 0, 64, 1e-3)])
+def test_fp32_preconditioner_solve(nx, ny, nt, alpha):
+    """FP32 transforms, FP64 Krylov: relres <= 1e-8 with at most 2 more iterations than
+    the FP64 path, solution close to the FP64 one."""
+    g = Grid(nx, ny, nt)
+    src, psi0, psi1 = synth.random_source(nx, ny, nt, seed=31)
+    f = aao.build_rhs(g, src, psi0, psi1)
+    p64 = _plan(nx, ny, nt, alpha=alpha)
+    u64, it64, rr64, st64 = p64.solve(_dev(f[None]), tol=1e-8, maxit=300)
+    p32 = _plan(nx, ny, nt, alpha=alpha, prec="fp32")
+    u32, it32, rr32, st32 = p32.solve(_dev(f[None]), tol=1e-8, maxit=300)
+    assert st64 == [0] and st32 == [0]
+    assert rr32[0] <= 1e-8
+    assert it32[0] <= it64[0] + 2
+    assert _rel(_host(u32)[0], _host(u64)[0]) < 1e-6
+
+
+def test_batch_equals_solo():
+    """Each right-hand side of a batched solve equals its solo solve bit for bit."""
+    nx, ny, nt, alpha = 15, 15, 16, 1e-3
+    B = 3
+    fs = []
+    for i in range(B):
+        g = Grid(nx, ny, nt)
+        src, psi0, psi1 = synth.jacobi_smoothed_source(nx, ny, nt, seed=4000 + i)
+        fs.append(aao.build_rhs(g, src, psi0, psi1))
+    pb = _plan(nx, ny, nt, alpha=alpha, batch=B)
+    ub, itb, rrb, stb = pb.solve(_dev(np.stack(fs)), tol=1e-8, maxit=200)
+    ubh = _host(ub)
+    for i in range(B):
+        ps = _plan(nx, ny, nt, alpha=alpha)
+        us, its, rrs, sts = ps.solve(_dev(fs[i][None]), tol=1e-8, maxit=200)
+        assert its[0] == itb[i] and sts[0] == stb[i] == 0
+        assert np.array_equal(_host(us)[0], ubh[i])
+
+
+def test_zero_rhs_and_breakdown_and_maxit():
+    nx, nt = 15, 16
+    p = _plan(nx, 0, nt, alpha=1e-2, batch=3)
+    f = np.zeros((3, nt, nx))
+    f[1] = np.random.default_rng(5).standard_normal((nt, nx))
+    f[2] = f[1]
+    f[2, 3, 4] = np.nan
+    u, iters, relres, status = p.solve(_dev(f), tol=1e-8, maxit=1)
+    assert status[0] == 0 and iters[0] == 0 and np.all(_host(u)[0] == 0)
+    assert status[1] == -4 and iters[1] == 1       # ABAC_ENOTCONV after maxit = 1
+    assert status[2] == -5                         # ABAC_EBREAKDOWN on NaN input
+
+
+def test_async_interface_matches_solve():
+    nx, ny, nt, alpha = 31, 31, 32, 1e-3
+    g = Grid(nx, ny, nt)
+    src, psi0, psi1 = synth.random_source(nx, ny, nt, seed=41)
+    f = _dev(aao.build_rhs(g, src, psi0, psi1)[None])
+    p = _plan(nx, ny, nt, alpha=alpha)
+    u1, it1, rr1, st1 = p.solve(f, tol=1e-8, maxit=100)
+    u2 = torch.empty_like(u1)
+    p.begin(f, u2, tol=1e-8, maxit=100)
+    for _ in range(100):
+        p.advance(1)
+        if p.poll():
+            break
+    it2, rr2, st2 = p.finish()
+    assert it1 == it2 and st1 == st2
+    assert torch.equal(u1, u2)
