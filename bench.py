@@ -1,0 +1,253 @@
+#!/usr/bin/env python
+"""Benchmark of the ABAC-preconditioned MINRES wave solver on one MI355X.
+
+A step is one whole solve: right-hand side assembly from device-resident source
+samples and initial data, then preconditioned MINRES to relative residual tol.
+Prints ONE JSON line on stdout (progress goes to stderr).
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--prec fp64|fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solves/s at rel. residual 1e-8 (FP32-precond vs FP64); p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: nx, ny, nt, alpha, batch, source recipe
+    "wave2d_255x255x256": dict(nx=255, ny=255, nt=256, alpha=1e-3, batch=1, source="manufactured2d"),
+    "wave2d_511x511x512": dict(nx=511, ny=511, nt=512, alpha=1e-3, batch=1, source="gaussian_field"),
+    "batch64_wave2d_127x127x128": dict(nx=127, ny=127, nt=128, alpha=1e-3, batch=64, source="jacobi"),
+    "wave1d_63x64": dict(nx=63, ny=0, nt=64, alpha=1e-3, batch=1, source="manufactured1d"),
+}
+KERNEL_CLASSES = ["stencil", "dstx_fwd", "dsty", "time", "dstx_inv", "update", "residual", "init", "rhs", "fin"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_inputs(w):
+    import synth
+    nx, ny, nt, B = w["nx"], w["ny"], w["nt"], w["batch"]
+    srcs, p0s, p1s = [], [], []
+    for b in range(B):
+        if w["source"] == "manufactured2d":
+            src, p0, p1, _ = synth.manufactured_2d(nx, ny, nt)
+        elif w["source"] == "manufactured1d":
+            src, p0, p1, _ = synth.manufactured_1d(nx, nt, noise_std=0.1, seed=1)
+        elif w["source"] == "gaussian_field":
+            src, p0, p1 = synth.gaussian_field_source(nx, ny, nt, seed=3)
+        elif w["source"] == "jacobi":
+            src, p0, p1 = synth.jacobi_smoothed_source(nx, ny, nt, seed=4000 + b)
+        else:
+            raise ValueError(w["source"])
+        srcs.append(src)
+        p0s.append(p0)
+        p1s.append(p1)
+    return np.stack(srcs), np.stack(p0s), np.stack(p1s)
+
+
+def algorithmic_bytes(w, prec, iters_total, solves):
+    """Algorithmic HBM bytes of every kernel class over `solves` solves that took
+    `iters_total` MINRES iterations in total (summed over right-hand sides).
+
+    Per right-hand side, with N unknowns, NS = nt*(nx+1)*max(ny,1) scratch values of
+    s bytes (8 for FP64, 4 for FP32 transforms):
+      stencil   16 N           (read z, write A z) per iteration
+      dstx_fwd  32 N + s NS    (read A z, v_j, v_{j-1}; write q; write scratch) per
+                8 N + s NS      iteration, plus the set-up pass (read b)
+      dsty      2 s NS         (read + write scratch) per launch, 2 launches per apply
+      time      2 s NS         (read + write scratch) per apply
+      dstx_inv  s NS + 16 N    (read scratch, write p, read q) per apply
+      update    72 N           (read z, w1, w2, x, r, v; write w, x, r) per iteration
+      init      56 N           (read f; write r, v1, v0, w0, w1, u) per solve
+    """
+    nx, ny, nt = w["nx"], w["ny"], w["nt"]
+    N = nt * nx * max(ny, 1)
+    NS = nt * (nx + 1) * max(ny, 1)
+    s = 8 if prec == "fp64" else 4
+    applies = iters_total + solves
+    return {
+        "stencil": 16 * N * iters_total,
+        "dstx_fwd": (32 * N + s * NS) * iters_total + (8 * N + s * NS) * solves,
+        "dsty": 2 * (2 * s * NS) * applies if ny else 0,
+        "time": 2 * s * NS * applies,
+        "dstx_inv": (s * NS + 16 * N) * applies,
+        "update": 72 * N * iters_total,
+        "init": 56 * N * solves,
+    }
+
+
+def pmc_traffic(kernel_class, workload, prec):
+    """Per-launch HBM bytes from a committed rocprofv3 counter summary, if it was taken
+    on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel_class}_{workload}_{prec}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha") != source_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def source_sha():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2306_03574_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def run_gpu(w, prec, steps, warmup, tol, maxit, profile=True):
+    import torch
+    from paper_2306_03574_amd import Plan
+    dev = torch.device("cuda:0")
+    src, p0, p1 = make_inputs(w)
+    d_src = torch.from_numpy(src).to(dev)
+    d_p0 = torch.from_numpy(p0).to(dev)
+    d_p1 = torch.from_numpy(p1).to(dev)
+    del src
+    plan = Plan(w["nx"], w["ny"], w["nt"], T=1.0, alpha=w["alpha"], prec=prec, batch=w["batch"], device=dev)
+    f = plan.empty()
+    u = plan.empty()
+    for i in range(warmup):
+        plan.build_rhs(d_src, d_p0, d_p1, f)
+        plan.solve(f, u, tol=tol, maxit=maxit)
+    torch.cuda.synchronize()
+    if profile:
+        plan.profile(True)
+        plan.profile_reset()
+    lat = []
+    iters_total = 0
+    last = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ts = time.perf_counter()
+        plan.build_rhs(d_src, d_p0, d_p1, f)
+        last = plan.solve(f, u, tol=tol, maxit=maxit)
+        lat.append(time.perf_counter() - ts)
+        iters_total += sum(last[1])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = {}
+    if profile:
+        for k in KERNEL_CLASSES:
+            ms, n = plan.profile_read(k)
+            prof[k] = {"ms": ms, "launches": n}
+        plan.profile(False)
+    _, iters, relres, status = last
+    u_host = u.cpu().numpy()
+    return dict(elapsed=elapsed, lat=lat, iters=iters, relres=relres, status=status, iters_total=iters_total,
+                prof=prof, u=u_host)
+
+
+def cpu_baseline(w, tol, maxit):
+    """The oracle, as it stands, on one whole solve of the same workload (first
+    right-hand side only for batched workloads)."""
+    from oracle.discretization import Grid, L_matrix
+    from oracle import allatonce as aao, preconditioner as pc, minres as mr
+    g = Grid(w["nx"], w["ny"], w["nt"], 1.0)
+    src, p0, p1 = make_inputs(dict(w, batch=1))
+    L = L_matrix(g)
+    c0, t0 = time.process_time(), time.perf_counter()
+    f = aao.build_rhs(g, src[0], p0[0], p1[0])
+    res = mr.minres(lambda v: aao.apply_A(g, v, L), lambda y: pc.apply_Pinv(g, w["alpha"], y),
+                    aao.reverse_time(f), tol=tol, maxit=maxit)
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    return dict(value=1.0 / wall, unit="solves/s", cores=max(1, int(round(cpu / wall))), kind="oracle",
+                sample=f"one whole FP64 oracle solve of the same workload ({res.iters} iterations, "
+                       f"{wall:.1f} s wall, {os.cpu_count()} host cores visible)", iters=res.iters, x=res.x)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="wave2d_255x255x256", choices=sorted(WORKLOADS))
+    ap.add_argument("--prec", default=None, choices=["fp64", "fp32"])
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--maxit", type=int, default=500)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the other-precision comparison leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the solver is single-GPU; see DESIGN.md for "
+              "how it would shard). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    w = WORKLOADS[args.workload]
+    prec = args.prec or ("fp32" if args.workload == "wave2d_511x511x512" else "fp64")
+    other = "fp32" if prec == "fp64" else "fp64"
+    log(f"workload {args.workload} prec {prec} steps {args.steps} warmup {args.warmup}")
+    main_run = run_gpu(w, prec, args.steps, args.warmup, args.tol, args.maxit)
+    log(f"{prec}: {args.steps / main_run['elapsed']:.2f} solves/s iters {main_run['iters'][:4]} "
+        f"relres {max(main_run['relres']):.2e}")
+    B = w["batch"]
+    solves = args.steps * B
+    value = solves / main_run["elapsed"]
+    lat_ms = np.array(main_run["lat"]) * 1e3
+
+    # roofline of the dominant kernel class over the timed region
+    prof = main_run["prof"]
+    dom = max((k for k in prof if prof[k]["launches"] > 0), key=lambda k: prof[k]["ms"])
+    abytes = algorithmic_bytes(w, prec, main_run["iters_total"], args.steps)
+    launches = prof[dom]["launches"]
+    avg_s = prof[dom]["ms"] / 1e3 / launches
+    bytes_per_launch = abytes.get(dom, 0) / launches
+    achieved = bytes_per_launch / avg_s / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(dom, args.workload, prec),
+                "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": int(bytes_per_launch)}
+    kernel_table = {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
+                        "GB/s": round(abytes[k] / (v["ms"] / 1e3) / 1e9, 1) if k in abytes and v["ms"] > 0 else None}
+                    for k, v in prof.items() if v["launches"]}
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(main_run["elapsed"] / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f64-krylov/f32-transforms", "data": "synthetic",
+        "config": {"workload": args.workload, "nx": w["nx"], "ny": w["ny"], "nt": w["nt"], "T": 1.0,
+                   "alpha": w["alpha"], "batch": B, "tol": args.tol, "precond_precision": prec,
+                   "source": w["source"]},
+        "p50_ms": round(float(np.percentile(lat_ms, 50)), 3), "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+        "iters": main_run["iters"][:8], "relres_max": max(main_run["relres"]),
+        "roofline": roofline, "kernels": kernel_table,
+    }
+    if not args.no_compare:
+        log(f"comparison leg: {other}")
+        cmp_run = run_gpu(w, other, max(3, args.steps // 2), 1, args.tol, args.maxit, profile=False)
+        cmp_val = max(3, args.steps // 2) * B / cmp_run["elapsed"]
+        diff = float(np.max(np.abs(cmp_run["u"] - main_run["u"])) / np.max(np.abs(main_run["u"])))
+        out[f"{other}_precond"] = {"value": round(cmp_val, 3), "unit": "solves/s", "iters": cmp_run["iters"][:8],
+                                   "relres_max": max(cmp_run["relres"]), "rel_diff_vs_" + prec: diff}
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle solve on the host")
+        cb = cpu_baseline(w, args.tol, args.maxit)
+        err = float(np.max(np.abs(main_run["u"][0] - cb["x"])) / np.max(np.abs(cb["x"])))
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"]["value"] = round(cb["value"], 5)
+        out["gpu_vs_oracle_rel_err"] = err
+        out["oracle_iters"] = cb["iters"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

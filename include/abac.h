@@ -130,7 +130,8 @@ enum {
   ABAC_K_RESIDUAL = 6,  /* explicit residual check                      */
   ABAC_K_INIT = 7,      /* solve set-up                                 */
   ABAC_K_RHS = 8,       /* right-hand side assembly                     */
-  ABAC_K_COUNT = 9
+  ABAC_K_FIN = 9,       /* per-RHS scalar steps (sums of partials)      */
+  ABAC_K_COUNT = 10
 };
 abac_status abac_profile_enable(abac_plan *plan, int on);
 abac_status abac_profile_read(abac_plan *plan, int kernel, double *total_ms, long long *launches);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -81,6 +82,7 @@ abac_status describe(int nx, int ny, int nt, double T, double alpha, int prec, i
     P.c0 += 2.0 * P.cy;
   }
   P.maxparts = std::max(stencil_blocks(P), std::max(update_blocks(P), dstx_blocks(P, prec)));
+  P.maxparts = (P.maxparts + 63) & ~63;
   return ABAC_OK;
 }
 
@@ -100,7 +102,7 @@ Layout make_layout(const DevPlan& P, int prec) {
   Lo.scratch = take(real * (size_t)P.NS * P.B);
   for (int i = 0; i < 8; ++i) Lo.vec[i] = take(sizeof(double) * (size_t)P.N * P.B);
   Lo.st = take(sizeof(MinresState) * P.B);
-  Lo.partials = take(sizeof(double) * (size_t)P.maxparts * P.B);
+  Lo.partials = take(sizeof(double) * (size_t)P.maxparts * P.B * PART_KINDS);
   Lo.counters = take(sizeof(unsigned) * P.B);
   Lo.total = o;
   return Lo;
@@ -127,12 +129,14 @@ struct abac_plan {
   MinresState* h_ring;   // pinned, kRing * B states
   hipEvent_t ring_ev[kRing];
   long long ring_posted;  // number of state snapshots enqueued
+  long long ring_base;    // first snapshot of the current solve
   const double* f;
   double* u;
   bool active;
   // kernel timing
   bool prof;
   std::vector<ProfPair> pending;
+  std::vector<hipEvent_t> event_pool;
   double prof_ms[ABAC_K_COUNT];
   long long prof_n[ABAC_K_COUNT];
 };
@@ -143,8 +147,14 @@ template <typename F>
 abac_status run_kernel(abac_plan* p, int kid, F&& launch, const char* what) {
   ProfPair pp{kid, nullptr, nullptr};
   if (p->prof) {
-    HIP_TRY(hipEventCreate(&pp.e0));
-    HIP_TRY(hipEventCreate(&pp.e1));
+    for (hipEvent_t* e : {&pp.e0, &pp.e1}) {
+      if (!p->event_pool.empty()) {
+        *e = p->event_pool.back();
+        p->event_pool.pop_back();
+      } else {
+        HIP_TRY(hipEventCreate(e));
+      }
+    }
     HIP_TRY(hipEventRecord(pp.e0, p->stream));
   }
   hipError_t e = launch();
@@ -164,8 +174,8 @@ abac_status flush_prof(abac_plan* p) {
     HIP_TRY(hipEventElapsedTime(&ms, pp.e0, pp.e1));
     p->prof_ms[pp.kid] += ms;
     p->prof_n[pp.kid] += 1;
-    (void)hipEventDestroy(pp.e0);
-    (void)hipEventDestroy(pp.e1);
+    p->event_pool.push_back(pp.e0);
+    p->event_pool.push_back(pp.e1);
   }
   p->pending.clear();
   return ABAC_OK;
@@ -191,16 +201,19 @@ abac_status enqueue_pinv(abac_plan* p, const double* r, double* z, int minres_mo
   if (P.ny) RUN(ABAC_K_DSTY, launch_dsty(P, p->prec, check, p->stream));
   const int inv_mode = minres_mode == 0 ? INV_PLAIN : (minres_mode == 1 ? INV_GAMMA_INIT : INV_GAMMA_ITER);
   RUN(ABAC_K_DSTX_INV, launch_dstx_inv(P, p->prec, inv_mode, z, p->stream));
+  if (minres_mode) RUN(ABAC_K_FIN, launch_fin(P, minres_mode == 1 ? FIN_GAMMA_INIT : FIN_GAMMA_ITER, 0.0, 0, p->stream));
   return ABAC_OK;
 }
 
 abac_status enqueue_iteration(abac_plan* p) {
   const DevPlan& P = p->P;
   RUN(ABAC_K_STENCIL, launch_stencil(P, STENCIL_MINRES, nullptr, nullptr, nullptr, p->stream));
+  RUN(ABAC_K_FIN, launch_fin(P, FIN_DELTA, 0.0, 0, p->stream));
   abac_status s = enqueue_pinv(p, nullptr, nullptr, 2);
   if (s != ABAC_OK) return s;
   RUN(ABAC_K_UPDATE, launch_update(P, p->u, p->stream));
   RUN(ABAC_K_RESIDUAL, launch_stencil(P, STENCIL_RESIDUAL, p->u, nullptr, p->f, p->stream));
+  RUN(ABAC_K_FIN, launch_fin(P, FIN_RES, 0.0, 0, p->stream));
   return ABAC_OK;
 }
 
@@ -389,6 +402,7 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
     return hip_fail(e, "host ring");
   }
   p->ring_posted = 0;
+  p->ring_base = 0;
   p->f = nullptr;
   p->u = nullptr;
   p->active = false;
@@ -405,6 +419,7 @@ abac_status abac_plan_destroy(abac_plan* p) {
   if (!p) return ABAC_OK;
   (void)hipStreamSynchronize(p->stream);
   flush_prof(p);
+  for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
   for (int i = 0; i < kRing; ++i) (void)hipEventDestroy(p->ring_ev[i]);
   if (p->h_ring) (void)hipHostFree(p->h_ring);
   if (p->own_ws) (void)hipFree(p->ws);
@@ -437,6 +452,7 @@ abac_status abac_minres_begin(abac_plan* p, const double* f, double* u, double t
   p->f = f;
   p->u = u;
   p->active = true;
+  p->ring_base = p->ring_posted;
   RUN(ABAC_K_INIT, launch_init(p->P, f, u, tol, maxit, p->stream));
   abac_status s = enqueue_pinv(p, nullptr, nullptr, 1);
   if (s != ABAC_OK) return s;
@@ -460,7 +476,7 @@ abac_status abac_minres_poll(abac_plan* p, int* done) {
     return ABAC_OK;
   }
   // newest completed snapshot
-  for (long long k = p->ring_posted - 1; k >= 0 && k >= p->ring_posted - kRing; --k) {
+  for (long long k = p->ring_posted - 1; k >= p->ring_base && k >= p->ring_posted - kRing; --k) {
     const int slot = (int)(k % kRing);
     hipError_t e = hipEventQuery(p->ring_ev[slot]);
     if (e == hipSuccess) {
@@ -475,6 +491,7 @@ abac_status abac_minres_poll(abac_plan* p, int* done) {
 abac_status abac_minres_finish(abac_plan* p, int* iters, double* relres, int* status) {
   if (!p || !p->active) return fail(ABAC_EINVAL, "no solve in progress");
   RUN(ABAC_K_RESIDUAL, launch_stencil(p->P, STENCIL_REPORT, p->u, nullptr, p->f, p->stream));
+  RUN(ABAC_K_FIN, launch_fin(p->P, FIN_REPORT, 0.0, 0, p->stream));
   std::vector<MinresState> h(p->P.B);
   HIP_TRY(hipMemcpyAsync(h.data(), p->P.st, sizeof(MinresState) * p->P.B, hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
@@ -488,16 +505,41 @@ abac_status abac_minres_solve(abac_plan* p, const double* f, double* u, double t
                               double* relres, int* status) {
   abac_status s = abac_minres_begin(p, f, u, tol, maxit);
   if (s != ABAC_OK) return s;
-  const int lag = 2;  // iterations kept queued ahead of the newest observed state
-  for (int it = 0; it < maxit; ++it) {
-    s = abac_minres_advance(p, 1);
-    if (s != ABAC_OK) return s;
-    const long long want = p->ring_posted - 1 - lag;
-    if (want >= 0) {
-      const int slot = (int)(want % kRing);
-      HIP_TRY(hipEventSynchronize(p->ring_ev[slot]));
-      if (all_stopped(p->h_ring + (size_t)slot * p->P.B, p->P.B)) break;
+  // Keep up to kAhead iterations queued beyond the newest observed state while the
+  // observed residual decay predicts that convergence is further away; near the
+  // predicted stop, step one iteration at a time so no idle iterations are queued.
+  const int kAhead = 2;
+  const int B = p->P.B;
+  long long enq = 0, obs = 0;
+  long long est = LLONG_MAX;
+  double rel_last = -1.0;
+  while (true) {
+    if (enq < maxit && enq - obs <= kAhead && enq < est) {
+      s = abac_minres_advance(p, 1);
+      if (s != ABAC_OK) return s;
+      ++enq;
+      continue;
     }
+    if (obs >= enq) {
+      if (enq >= maxit) break;
+      est = enq + 1;   // prediction was early: take one more step
+      continue;
+    }
+    const int slot = (int)((p->ring_base + obs + 1) % kRing);
+    HIP_TRY(hipEventSynchronize(p->ring_ev[slot]));
+    ++obs;
+    const MinresState* snap = p->h_ring + (size_t)slot * B;
+    if (all_stopped(snap, B)) break;
+    double rel = 0.0;
+    for (int b = 0; b < B; ++b)
+      if (snap[b].state == ST_RUNNING && snap[b].bnorm2 > 0) rel = std::max(rel, std::sqrt(snap[b].rnorm2 / snap[b].bnorm2));
+    if (rel_last > 0.0 && rel > 0.0 && rel < rel_last) {
+      const double rem = std::ceil(std::log(tol / rel) / std::log(rel / rel_last));
+      est = obs + (long long)std::max(1.0, std::min(rem, 1e6));
+    } else {
+      est = LLONG_MAX;
+    }
+    rel_last = rel;
   }
   return abac_minres_finish(p, iters, relres, status);
 }

@@ -32,8 +32,9 @@ struct MinresState {
   int state;        // ST_*
   int status;       // abac_status of this right-hand side
   int explicit_mode;
-  int need_check;
-  int pad0, pad1;
+  int need_check;   // set by the residual kernel: confirm convergence explicitly
+  int lucky;        // gamma_{j+1} == 0: the Krylov space is invariant
+  int pad0;
 };
 
 // Everything a kernel needs about a plan, passed by value.
@@ -63,16 +64,22 @@ struct DevPlan {
   double* W[2];
   double* R;
   MinresState* st;     // B entries
-  double* partials;    // B * maxparts
+  double* partials;    // PART_KINDS * B * maxparts
   unsigned* counters;  // B entries
   int maxparts;
   int pad2_;
 };
 
 // ---------------------------------------------------------------------------
-// deterministic reductions: fixed-order block sums, partials per block, and a
-// last-block-done finalisation that sums the partials in index order.
+// deterministic reductions: every block of a reducing kernel writes one partial
+// (fixed-order block sum) into its own slot; a later kernel sums the slots in index
+// order.  Kernel boundaries provide the visibility, so no fences or atomics are used.
 // ---------------------------------------------------------------------------
+enum PartKind : int { PART_DELTA = 0, PART_GAMMA = 1, PART_RNORM = 2, PART_RES = 3, PART_KINDS = 4 };
+
+__device__ __forceinline__ double* part_slot(const DevPlan& P, int kind, int b) {
+  return P.partials + ((size_t)kind * P.B + b) * P.maxparts;
+}
 
 // Sum of v over the block; the result is valid in thread 0.  Ends with a barrier so
 // the shared buffer can be reused.
@@ -92,33 +99,11 @@ __device__ __forceinline__ double block_sum(double v) {
   return s;
 }
 
-// Publish this block's partial for right-hand side b and report whether the block
-// is the last of the nblocks contributing ones.  Uniform result across the block.
-__device__ __forceinline__ bool arrive_last(const DevPlan& P, int b, int blk, int nblocks, double partial) {
-  __shared__ int amlast;
-  if (threadIdx.x == 0) {
-    P.partials[(size_t)b * P.maxparts + blk] = partial;
-    __threadfence();
-    const unsigned t = atomicAdd(P.counters + b, 1u);
-    amlast = (t == (unsigned)(nblocks - 1));
-  }
-  __syncthreads();
-  const bool last = amlast != 0;
-  if (last) __threadfence();
-  return last;
-}
-
-// In the last block: fixed-order sum of the nblocks partials (result in thread 0),
-// and the counter reset for the next reduction.
-__device__ __forceinline__ double finish_sum(const DevPlan& P, int b, int nblocks) {
-  const volatile double* part = P.partials + (size_t)b * P.maxparts;
+// Fixed-order sum of n partials by the whole block; result valid in thread 0.
+__device__ __forceinline__ double sum_parts(const double* __restrict__ part, int n) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) s += part[i];
-  s = block_sum(s);
-  if (threadIdx.x == 0) {
-    atomicExch(P.counters + b, 0u);
-  }
-  return s;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  return block_sum(s);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap the hardware block
@@ -136,8 +121,18 @@ __device__ __forceinline__ int xcd_remap(int w, int n) {
 enum StencilMode : int { STENCIL_PLAIN = 0, STENCIL_MINRES = 1, STENCIL_RESIDUAL = 2, STENCIL_REPORT = 3 };
 enum FwdMode : int { FWD_PLAIN = 0, FWD_LANCZOS = 1 };
 enum InvMode : int { INV_PLAIN = 0, INV_GAMMA_INIT = 1, INV_GAMMA_ITER = 2 };
+enum FinKind : int { FIN_BNORM = 0, FIN_DELTA = 1, FIN_GAMMA_INIT = 2, FIN_GAMMA_ITER = 3, FIN_RES = 4, FIN_REPORT = 5 };
 
-int stencil_blocks(const DevPlan& P);
+// matvec decomposition: 256 spatial points per block, 32 forward time levels (plus
+// their mirrors) per block
+constexpr int kStencilThreads = 256;
+constexpr int kChunk = 32;
+__host__ __device__ inline int stencil_blocks(const DevPlan& P) {
+  const int tiles = (P.m + kStencilThreads - 1) / kStencilThreads;
+  const int nchunks = (P.nt / 2 + kChunk - 1) / kChunk;
+  return tiles * nchunks;
+}
+int stencil_grid(const DevPlan& P, int mode);
 int update_blocks(const DevPlan& P);
 int dstx_blocks(const DevPlan& P, int prec);
 
@@ -146,6 +141,9 @@ hipError_t launch_rhs(const DevPlan& P, const double* src, const double* psi0, c
                       hipStream_t s);
 hipError_t launch_init(const DevPlan& P, const double* f, double* u, double tol, int maxit, hipStream_t s);
 hipError_t launch_update(const DevPlan& P, double* u, hipStream_t s);
+// one block per right-hand side: fixed-order sum of the partials of a reduction and
+// the scalar step that consumes it
+hipError_t launch_fin(const DevPlan& P, int kind, double tol, int maxit, hipStream_t s);
 
 // check != 0: skip right-hand sides whose solve is not running
 hipError_t launch_dstx_fwd(const DevPlan& P, int prec, int mode, int check, const double* in, hipStream_t s);

@@ -167,13 +167,21 @@ __device__ __forceinline__ int stockham_dst(int b, int Ns, int i) {
 // v[i] = X[j + i*TPS].  All threads of the workgroup must call it together.  The
 // LDS region lds[e*S] (e < L) must be free on entry (the caller puts a barrier
 // between its last LDS reads and this call); on return other threads may still be
-// reading it, so the caller must barrier before writing it again.
-template <typename T, int L, bool INV>
+// reading it, so the caller must barrier before writing it again.  With FROM_LDS the
+// input is read from lds[e*S] in natural order instead (the caller barriers after
+// writing it).
+template <typename T, int L, bool INV, bool FROM_LDS = false>
 __device__ __forceinline__ void fft_seq(cplx<T>* v, int j, cplx<T>* lds, int S, const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
   using Sh = FftShape<L>;
   constexpr int R = Sh::R;
   constexpr int TPS = L / R;
+  if constexpr (FROM_LDS) {
+    // input in natural order in LDS (written and fenced by the caller)
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = lds[(j + i * TPS) * S];
+    __syncthreads();
+  }
   // pass 0: radix R, Ns = 1
   dftR<R, INV>(v);
   if constexpr (Sh::passes == 1) {

@@ -4,17 +4,18 @@
 //     nt-1-k of z without a second read of z;
 //   * the explicit residual ||f - T u|| used to confirm convergence;
 //   * right-hand side assembly of eq. (1.2);
-//   * solve set-up and the MINRES w / x / r update with its residual norm.
+//   * solve set-up, the MINRES w / x / r update and the scalar steps (Givens QR of the
+//     Lanczos tridiagonal matrix, stopping test) run by one block per right-hand side.
 #include "abac_internal.h"
 
 namespace abac {
 
 namespace {
 
-constexpr int kStencilThreads = 256;
-constexpr int kChunk = 32;          // forward time levels per block (plus the mirrored ones)
+constexpr int kResidualGrid = 256;  // blocks of the (usually idle) explicit residual check
 constexpr int kVecThreads = 256;
-constexpr int kVecPerThread = 4;
+constexpr int kVecPerThread = 16;
+constexpr int kVecMaxBlocks = 1024;
 
 // (L s)_i at spatial point (ix, iy) of one level, zero Dirichlet ghosts.
 __device__ __forceinline__ double apply_L(const DevPlan& P, const double* __restrict__ lvl, int i, int ix, int iy) {
@@ -29,96 +30,96 @@ __device__ __forceinline__ double apply_L(const DevPlan& P, const double* __rest
   return P.c0 * c - P.cx * sx - P.cy * sy;
 }
 
+// One logical block of the matvec: spatial tile `tile`, forward levels [k0, k1) and
+// their mirrors nt-1-k.  Returns this thread's contribution to the fused reduction.
+__device__ __forceinline__ double stencil_tile(const DevPlan& P, int mode, const double* __restrict__ x,
+                                               double* __restrict__ y, const double* __restrict__ f, int tile,
+                                               int chunk) {
+  const int n = P.nt, m = P.m;
+  const int i = tile * kStencilThreads + threadIdx.x;
+  if (i >= m) return 0.0;
+  const int ix = i % P.nx, iy = i / P.nx;
+  const int k0 = chunk * kChunk;
+  const int k1 = min(k0 + kChunk, n / 2);
+  double acc = 0.0;
+  // forward march state: x_{k-1}, x_{k-2} and L of them
+  double zf1 = 0.0, zf2 = 0.0, Lf1 = 0.0, Lf2 = 0.0;
+  if (k0 >= 2) { zf2 = x[(size_t)(k0 - 2) * m + i]; Lf2 = apply_L(P, x + (size_t)(k0 - 2) * m, i, ix, iy); }
+  if (k0 >= 1) { zf1 = x[(size_t)(k0 - 1) * m + i]; Lf1 = apply_L(P, x + (size_t)(k0 - 1) * m, i, ix, iy); }
+  // backward march state at kb = n-1-k0: x_kb, x_{kb-1} and L of them
+  const int kb0 = n - 1 - k0;
+  double zb0 = x[(size_t)kb0 * m + i], Lb0 = apply_L(P, x + (size_t)kb0 * m, i, ix, iy);
+  double zb1 = x[(size_t)(kb0 - 1) * m + i], Lb1 = apply_L(P, x + (size_t)(kb0 - 1) * m, i, ix, iy);
+  for (int k = k0; k < k1; ++k) {
+    const double* lk = x + (size_t)k * m;
+    const double zk = lk[i];
+    const double Lk = apply_L(P, lk, i, ix, iy);
+    const double out_f = Lk + Lf2 - 2.0 * zf1;          // (T x)_k
+    const int kb = n - 1 - k;
+    const double* lb2 = x + (size_t)(kb - 2) * m;
+    const double zb2 = lb2[i];
+    const double Lb2 = apply_L(P, lb2, i, ix, iy);
+    const double out_b = Lb0 + Lb2 - 2.0 * zb1;         // (T x)_kb
+    if (mode >= STENCIL_RESIDUAL) {
+      const double rf = f[(size_t)k * m + i] - out_f;
+      const double rb = f[(size_t)kb * m + i] - out_b;
+      acc += rf * rf + rb * rb;
+    } else {
+      y[(size_t)(n - 1 - k) * m + i] = out_f;           // Y reverses time
+      y[(size_t)(n - 1 - kb) * m + i] = out_b;
+      if (mode == STENCIL_MINRES) acc += out_f * zb0 + out_b * zk;
+    }
+    zf2 = zf1; Lf2 = Lf1; zf1 = zk; Lf1 = Lk;
+    zb0 = zb1; Lb0 = Lb1; zb1 = zb2; Lb1 = Lb2;
+  }
+  return acc;
+}
+
 __global__ void __launch_bounds__(kStencilThreads)
 k_stencil(DevPlan P, int mode, const double* __restrict__ xin, double* __restrict__ yout,
-          const double* __restrict__ fref) {
+          const double* __restrict__ fref, int nparts_rnorm) {
   const int b = blockIdx.y;
   MinresState* st = P.st + b;
   const double* x = xin;
   double* y = yout;
-  if (mode == STENCIL_MINRES || mode == STENCIL_RESIDUAL) {
+  int part_kind = PART_RES;
+  if (mode == STENCIL_MINRES) {
     if (st->state != ST_RUNNING) return;
-    if (mode == STENCIL_RESIDUAL && !st->need_check) return;
-    if (mode == STENCIL_MINRES) {
-      const int j = st->iter + 1;
-      x = P.Z[j & 1];
-      y = P.V[(j + 1) % 3];
+    const int j = st->iter + 1;
+    x = P.Z[j & 1];
+    y = P.V[(j + 1) % 3];
+    part_kind = PART_DELTA;
+  } else if (mode == STENCIL_RESIDUAL) {
+    // stopping test on the recurrence residual of the update kernel (same fixed-order
+    // sum in every block); confirm explicitly when it passes
+    if (st->state != ST_RUNNING) return;
+    const double rn2 = sum_parts(part_slot(P, PART_RNORM, b), nparts_rnorm);
+    __shared__ int need_sh;
+    if (threadIdx.x == 0) {
+      const int need = (rn2 <= st->tol2 * st->bnorm2) || st->explicit_mode || st->iter >= st->maxit || st->lucky ||
+                       !(rn2 == rn2);
+      need_sh = need;
+      if (blockIdx.x == 0) {
+        st->rnorm2 = rn2;
+        st->need_check = need;
+      }
     }
+    __syncthreads();
+    if (!need_sh) return;
   }
   x += (size_t)b * P.N;
   if (y) y += (size_t)b * P.N;
   const double* f = fref ? fref + (size_t)b * P.N : nullptr;
-
-  const int n = P.nt, m = P.m;
-  const int tiles = (m + kStencilThreads - 1) / kStencilThreads;
-  const int nchunks = (n / 2 + kChunk - 1) / kChunk;
-  const int nblk = tiles * nchunks;
-  const int lb = xcd_remap(blockIdx.x, nblk);
-  const int tile = lb % tiles, chunk = lb / tiles;
-  const int i = tile * kStencilThreads + threadIdx.x;
-  const bool act = i < m;
-  const int ix = act ? i % P.nx : 0, iy = act ? i / P.nx : 0;
-  const int k0 = chunk * kChunk;
-  const int k1 = min(k0 + kChunk, n / 2);
-
+  const int tiles = (P.m + kStencilThreads - 1) / kStencilThreads;
+  const int nblk = stencil_blocks(P);
   double acc = 0.0;
-  if (act) {
-    // forward march state: x_{k-1}, x_{k-2} and L of them
-    double zf1 = 0.0, zf2 = 0.0, Lf1 = 0.0, Lf2 = 0.0;
-    if (k0 >= 2) { zf2 = x[(size_t)(k0 - 2) * m + i]; Lf2 = apply_L(P, x + (size_t)(k0 - 2) * m, i, ix, iy); }
-    if (k0 >= 1) { zf1 = x[(size_t)(k0 - 1) * m + i]; Lf1 = apply_L(P, x + (size_t)(k0 - 1) * m, i, ix, iy); }
-    // backward march state at kb = n-1-k0: x_kb, x_{kb-1} and L of them
-    const int kb0 = n - 1 - k0;
-    double zb0 = x[(size_t)kb0 * m + i], Lb0 = apply_L(P, x + (size_t)kb0 * m, i, ix, iy);
-    double zb1 = x[(size_t)(kb0 - 1) * m + i], Lb1 = apply_L(P, x + (size_t)(kb0 - 1) * m, i, ix, iy);
-    for (int k = k0; k < k1; ++k) {
-      const double* lk = x + (size_t)k * m;
-      const double zk = lk[i];
-      const double Lk = apply_L(P, lk, i, ix, iy);
-      const double out_f = Lk + Lf2 - 2.0 * zf1;          // (T x)_k
-      const int kb = n - 1 - k;
-      const double* lb2 = x + (size_t)(kb - 2) * m;
-      const double zb2 = lb2[i];
-      const double Lb2 = apply_L(P, lb2, i, ix, iy);
-      const double out_b = Lb0 + Lb2 - 2.0 * zb1;         // (T x)_kb
-      if (mode >= STENCIL_RESIDUAL) {
-        const double rf = f[(size_t)k * m + i] - out_f;
-        const double rb = f[(size_t)kb * m + i] - out_b;
-        acc += rf * rf + rb * rb;
-      } else {
-        y[(size_t)(n - 1 - k) * m + i] = out_f;           // Y reverses time
-        y[(size_t)(n - 1 - kb) * m + i] = out_b;
-        if (mode == STENCIL_MINRES) acc += out_f * zb0 + out_b * zk;
-      }
-      zf2 = zf1; Lf2 = Lf1; zf1 = zk; Lf1 = Lk;
-      zb0 = zb1; Lb0 = Lb1; zb1 = zb2; Lb1 = Lb2;
-    }
+  for (int w = blockIdx.x; w < nblk; w += gridDim.x) {
+    const int lb = xcd_remap(w, nblk);
+    acc += stencil_tile(P, mode, x, y, f, lb % tiles, lb / tiles);
   }
   if (mode == STENCIL_PLAIN) return;
   const double bs = block_sum(acc);
-  if (!arrive_last(P, b, blockIdx.x, nblk, bs)) return;
-  const double tot = finish_sum(P, b, nblk);
-  if (threadIdx.x != 0) return;
-  if (mode == STENCIL_MINRES) {
-    st->delta = tot * st->sig * st->sig;
-  } else if (mode == STENCIL_REPORT) {
-    st->res2 = tot;
-  } else {
-    st->res2 = tot;
-    if (tot <= st->tol2 * st->bnorm2) {
-      st->state = ST_DONE;
-      st->status = 0;
-    } else if (st->iter >= st->maxit) {
-      st->state = ST_DONE;
-      st->status = -4;  // ABAC_ENOTCONV
-    } else if (!(tot == tot) || tot > 1e300) {
-      st->state = ST_DONE;
-      st->status = -5;  // ABAC_EBREAKDOWN
-    } else {
-      st->explicit_mode = 1;
-    }
-    st->need_check = 0;
-  }
+  if (threadIdx.x == 0) part_slot(P, part_kind, b)[blockIdx.x] = bs;
 }
 
 // f_1 = tau^2 src_0 / 2 + tau psi1 + psi0; f_2 = tau^2 src_1 - L psi0; f_k = tau^2 src_{k-1}
@@ -142,9 +143,9 @@ k_rhs(DevPlan P, const double* __restrict__ src, const double* __restrict__ psi0
   }
 }
 
-// Set-up of a solve: b = Y f into R and V_1, zero V_0, W_0, W_1 and u, ||b||^2.
+// Set-up of a solve: b = Y f into R and V_1, zero V_0, W_0, W_1 and u; ||b||^2 partials.
 __global__ void __launch_bounds__(kVecThreads)
-k_init(DevPlan P, const double* __restrict__ f, double* __restrict__ u, double tol, int maxit) {
+k_init(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
   const int b = blockIdx.y;
   const size_t off = (size_t)b * P.N;
   const int nblk = gridDim.x;
@@ -165,34 +166,14 @@ k_init(DevPlan P, const double* __restrict__ f, double* __restrict__ u, double t
     acc += v * v;
   }
   const double bs = block_sum(acc);
-  if (!arrive_last(P, b, blockIdx.x, nblk, bs)) return;
-  const double tot = finish_sum(P, b, nblk);
-  if (threadIdx.x != 0) return;
-  MinresState* st = P.st + b;
-  st->bnorm2 = tot;
-  st->tol2 = tol * tol;
-  st->maxit = maxit;
-  st->iter = 0;
-  st->explicit_mode = 0;
-  st->need_check = 0;
-  st->rnorm2 = tot;
-  st->res2 = tot;
-  st->status = 0;
-  if (tot == 0.0) {
-    st->state = ST_DONE;   // u = 0 is exact
-  } else if (!(tot == tot) || tot > 1e300) {
-    st->state = ST_DONE;
-    st->status = -5;
-  } else {
-    st->state = ST_RUNNING;
-  }
+  if (threadIdx.x == 0) part_slot(P, PART_RNORM, b)[blockIdx.x] = bs;
 }
 
 // w_j = wa Z_j - wb w_{j-1} - wc w_{j-2};  x += xc w_j;  r = r1 r + r2 V_{j+1};  ||r||^2
 __global__ void __launch_bounds__(kVecThreads)
 k_update(DevPlan P, double* __restrict__ u) {
   const int b = blockIdx.y;
-  MinresState* st = P.st + b;
+  const MinresState* st = P.st + b;
   if (st->state != ST_RUNNING) return;
   const int j = st->iter;
   const double wa = st->wa, wb = st->wb, wc = st->wc, xc = st->xc, r1 = st->r1, r2 = st->r2;
@@ -217,32 +198,144 @@ k_update(DevPlan P, double* __restrict__ u) {
     acc += r * r;
   }
   const double bs = block_sum(acc);
-  if (!arrive_last(P, b, blockIdx.x, nblk, bs)) return;
-  const double tot = finish_sum(P, b, nblk);
+  if (threadIdx.x == 0) part_slot(P, PART_RNORM, b)[blockIdx.x] = bs;
+}
+
+// Lanczos coefficient gamma_{j+1} and the Givens QR update of iteration j.
+__device__ void step_gamma_iter(MinresState* st, double g2) {
+  if (!(g2 >= 0.0) || !(g2 < 1e300)) {
+    st->state = ST_DONE;
+    st->status = -5;  // ABAC_EBREAKDOWN
+    st->iter += 1;
+    return;
+  }
+  const double gn = sqrt(g2);
+  const double gam = st->gamma, del = st->delta;
+  const double eps = st->s2 * gam;
+  const double dbar = st->c2 * gam;
+  const double dp = st->c1 * dbar + st->s1 * del;
+  const double t2 = -st->s1 * dbar + st->c1 * del;
+  const double rho = hypot(t2, gn);
+  if (!(rho > 0.0) || !(rho < 1e300)) {
+    st->state = ST_DONE;
+    st->status = -5;
+    st->iter += 1;
+    return;
+  }
+  const double c = t2 / rho, s = gn / rho;
+  st->wa = st->sig / rho;
+  st->wb = dp / rho;
+  st->wc = eps / rho;
+  st->xc = c * st->eta;
+  st->r1 = s * s;
+  st->r2 = gn > 0.0 ? -s * c * st->eta / gn : 0.0;
+  st->eta = -s * st->eta;
+  st->c2 = st->c1; st->c1 = c;
+  st->s2 = st->s1; st->s1 = s;
+  st->sig_prev = st->sig;
+  st->sig = gn > 0.0 ? 1.0 / gn : 0.0;
+  st->gamma = gn;
+  st->iter += 1;
+  if (gn == 0.0) st->lucky = 1;
+}
+
+__global__ void __launch_bounds__(kVecThreads)
+k_fin(DevPlan P, int kind, int nparts, double tol, int maxit) {
+  const int b = blockIdx.x;
+  MinresState* st = P.st + b;
+  if (kind != FIN_BNORM && kind != FIN_REPORT && st->state != ST_RUNNING) return;
+  if (kind == FIN_RES && !st->need_check) return;
+  int pk = PART_RES;
+  switch (kind) {
+    case FIN_BNORM: pk = PART_RNORM; break;
+    case FIN_DELTA: pk = PART_DELTA; break;
+    case FIN_GAMMA_INIT:
+    case FIN_GAMMA_ITER: pk = PART_GAMMA; break;
+    default: pk = PART_RES; break;
+  }
+  const double tot = sum_parts(part_slot(P, pk, b), nparts);
   if (threadIdx.x != 0) return;
-  st->rnorm2 = tot;
-  if (tot <= st->tol2 * st->bnorm2 || st->explicit_mode || st->iter >= st->maxit || st->need_check)
-    st->need_check = 1;
+  switch (kind) {
+    case FIN_BNORM:
+      st->bnorm2 = tot;
+      st->tol2 = tol * tol;
+      st->maxit = maxit;
+      st->iter = 0;
+      st->explicit_mode = 0;
+      st->need_check = 0;
+      st->lucky = 0;
+      st->rnorm2 = tot;
+      st->res2 = tot;
+      st->status = 0;
+      if (tot == 0.0) {
+        st->state = ST_DONE;   // u = 0 is exact
+      } else if (!(tot == tot) || tot > 1e300) {
+        st->state = ST_DONE;
+        st->status = -5;
+      } else {
+        st->state = ST_RUNNING;
+      }
+      break;
+    case FIN_DELTA:
+      st->delta = tot * st->sig * st->sig;
+      break;
+    case FIN_GAMMA_INIT:
+      if (!(tot > 0.0) || !(tot < 1e300)) {
+        st->state = ST_DONE;
+        st->status = -5;
+        break;
+      }
+      st->gamma = sqrt(tot);
+      st->sig = 1.0 / st->gamma;
+      st->sig_prev = 0.0;
+      st->eta = st->gamma;
+      st->c1 = 1.0; st->c2 = 1.0;
+      st->s1 = 0.0; st->s2 = 0.0;
+      st->iter = 0;
+      break;
+    case FIN_GAMMA_ITER:
+      step_gamma_iter(st, tot);
+      break;
+    case FIN_RES:
+      st->res2 = tot;
+      if (tot <= st->tol2 * st->bnorm2) {
+        st->state = ST_DONE;
+        st->status = 0;
+      } else if (!(tot == tot) || tot > 1e300) {
+        st->state = ST_DONE;
+        st->status = -5;
+      } else if (st->iter >= st->maxit) {
+        st->state = ST_DONE;
+        st->status = -4;  // ABAC_ENOTCONV
+      } else {
+        st->explicit_mode = 1;
+      }
+      st->need_check = 0;
+      break;
+    case FIN_REPORT:
+      st->res2 = tot;
+      break;
+  }
 }
 
 }  // namespace
 
-int stencil_blocks(const DevPlan& P) {
-  const int tiles = (P.m + kStencilThreads - 1) / kStencilThreads;
-  const int nchunks = (P.nt / 2 + kChunk - 1) / kChunk;
-  return tiles * nchunks;
+int stencil_grid(const DevPlan& P, int mode) {
+  const int n = stencil_blocks(P);
+  if (mode == STENCIL_RESIDUAL || mode == STENCIL_REPORT) return n < kResidualGrid ? n : kResidualGrid;
+  return n;
 }
 
 int update_blocks(const DevPlan& P) {
   long long want = (P.N + (long long)kVecThreads * kVecPerThread - 1) / ((long long)kVecThreads * kVecPerThread);
-  if (want > 4096) want = 4096;
+  if (want > kVecMaxBlocks) want = kVecMaxBlocks;
   if (want < 1) want = 1;
   return (int)want;
 }
 
 hipError_t launch_stencil(const DevPlan& P, int mode, const double* x, double* y, const double* f, hipStream_t s) {
-  dim3 grid(stencil_blocks(P), P.B);
-  hipLaunchKernelGGL(k_stencil, grid, dim3(kStencilThreads), 0, s, P, mode, x, y, f);
+  dim3 grid(stencil_grid(P, mode), P.B);
+  hipLaunchKernelGGL(k_stencil, grid, dim3(kStencilThreads), 0, s, P, mode, x, y, f, update_blocks(P));
   return hipGetLastError();
 }
 
@@ -257,13 +350,28 @@ hipError_t launch_rhs(const DevPlan& P, const double* src, const double* psi0, c
 
 hipError_t launch_init(const DevPlan& P, const double* f, double* u, double tol, int maxit, hipStream_t s) {
   dim3 grid(update_blocks(P), P.B);
-  hipLaunchKernelGGL(k_init, grid, dim3(kVecThreads), 0, s, P, f, u, tol, maxit);
-  return hipGetLastError();
+  hipLaunchKernelGGL(k_init, grid, dim3(kVecThreads), 0, s, P, f, u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_fin(P, FIN_BNORM, tol, maxit, s);
 }
 
 hipError_t launch_update(const DevPlan& P, double* u, hipStream_t s) {
   dim3 grid(update_blocks(P), P.B);
   hipLaunchKernelGGL(k_update, grid, dim3(kVecThreads), 0, s, P, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_fin(const DevPlan& P, int kind, double tol, int maxit, hipStream_t s) {
+  int nparts;
+  switch (kind) {
+    case FIN_BNORM: nparts = update_blocks(P); break;
+    case FIN_DELTA: nparts = stencil_grid(P, STENCIL_MINRES); break;
+    case FIN_GAMMA_INIT:
+    case FIN_GAMMA_ITER: nparts = dstx_blocks(P, 0); break;
+    default: nparts = stencil_grid(P, STENCIL_RESIDUAL); break;
+  }
+  hipLaunchKernelGGL(k_fin, dim3(P.B), dim3(kVecThreads), 0, s, P, kind, nparts, tol, maxit);
   return hipGetLastError();
 }
 

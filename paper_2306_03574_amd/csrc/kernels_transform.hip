@@ -25,75 +25,24 @@ template <int L> constexpr int block_threads() { return seqs_per_block<L>() * ff
 
 template <typename T>
 __device__ __forceinline__ cplx<T> inv_sqrt_principal(cplx<T> mu) {
-  // 1/s(mu), s the principal square root: s(mu) = (w, y/(2w)) for x >= 0 and
-  // (|y|/(2w), sign(y) w) for x < 0 with w = sqrt((|mu| + |x|)/2); 1/s = conj(s)/|mu|.
+  // 1/s(mu), s the principal square root.  With |mu| = sqrt(x^2 + y^2) and
+  // w = sqrt((|mu| + |x|)/2):  s = (w, y/(2w)) for x >= 0 and (|y|/(2w), sign(y) w)
+  // for x < 0, and 1/s = conj(s)/|mu|.  Two reciprocal square roots, no division.
   const T x = mu.x, y = mu.y;
-  const T r = sqrt(x * x + y * y);
-  const T w = sqrt((r + fabs(x)) * (T)0.5);
+  const T rr = x * x + y * y;
+  const T g = rsqrt(rr);                 // 1/|mu|
+  const T w2 = (rr * g + fabs(x)) * (T)0.5;
+  const T h = rsqrt(w2);                 // 1/w
+  const T w = w2 * h;
   T sr, si;
   if (x >= (T)0) {
     sr = w;
-    si = y / (w + w);
+    si = (T)0.5 * y * h;
   } else {
-    sr = fabs(y) / (w + w);
+    sr = (T)0.5 * fabs(y) * h;
     si = copysign(w, y);
   }
-  const T ir = (T)1 / r;
-  return cplx<T>{sr * ir, -si * ir};
-}
-
-__device__ __forceinline__ void finalize_gamma_init(MinresState* st, double g2) {
-  if (!(g2 > 0.0) || !(g2 < 1e300)) {
-    st->state = ST_DONE;
-    st->status = -5;  // ABAC_EBREAKDOWN
-    return;
-  }
-  const double g = sqrt(g2);
-  st->gamma = g;
-  st->sig = 1.0 / g;
-  st->sig_prev = 0.0;
-  st->eta = g;
-  st->c1 = 1.0; st->c2 = 1.0;
-  st->s1 = 0.0; st->s2 = 0.0;
-  st->iter = 0;
-}
-
-// Lanczos coefficient gamma_{j+1} and the Givens QR update of iteration j.
-__device__ __forceinline__ void finalize_gamma_iter(MinresState* st, double g2) {
-  if (!(g2 >= 0.0) || !(g2 < 1e300)) {
-    st->state = ST_DONE;
-    st->status = -5;
-    st->iter += 1;
-    return;
-  }
-  const double gn = sqrt(g2);
-  const double gam = st->gamma, del = st->delta;
-  const double eps = st->s2 * gam;
-  const double dbar = st->c2 * gam;
-  const double dp = st->c1 * dbar + st->s1 * del;
-  const double t2 = -st->s1 * dbar + st->c1 * del;
-  const double rho = hypot(t2, gn);
-  if (!(rho > 0.0) || !(rho < 1e300)) {
-    st->state = ST_DONE;
-    st->status = -5;
-    st->iter += 1;
-    return;
-  }
-  const double c = t2 / rho, s = gn / rho;
-  st->wa = st->sig / rho;
-  st->wb = dp / rho;
-  st->wc = eps / rho;
-  st->xc = c * st->eta;
-  st->r1 = s * s;
-  st->r2 = gn > 0.0 ? -s * c * st->eta / gn : 0.0;
-  st->eta = -s * st->eta;
-  st->c2 = st->c1; st->c1 = c;
-  st->s2 = st->s1; st->s1 = s;
-  st->sig_prev = st->sig;
-  st->sig = gn > 0.0 ? 1.0 / gn : 0.0;
-  st->gamma = gn;
-  st->iter += 1;
-  if (gn == 0.0) st->need_check = 1;
+  return cplx<T>{sr * g, -si * g};
 }
 
 // ---------------------------------------------------------------------------
@@ -233,6 +182,34 @@ k_dsty(DevPlan P, int check) {
 // ---------------------------------------------------------------------------
 // time pass: per spatial mode pair, out = K Y K Y g, in place on the scratch.
 // ---------------------------------------------------------------------------
+// Spectral weights of two real modes packed as one complex sequence z = g_a + i g_b:
+// with Z = F z, the spectra of the two modes are (Z_k + conj Z_{-k})/2 and
+// (Z_k - conj Z_{-k})/(2i); weighting them by Ma_k, Mb_k and repacking gives
+//   Z'_k = ((Ma + Mb) Z_k + (Ma - Mb) conj Z_{-k}) / 2.
+// mu is Hermitian in k (mu_{-k} = conj mu_k), so one thread handles the pair
+// (k, nt-k) with a single evaluation of Ma_k, Mb_k.  Input and output in LDS, natural
+// order; `scale` folds in the 1/nt of the inverse DFT.
+template <typename T, int NT>
+__device__ __forceinline__ void spectral_pairs(cplx<T>* my, int S, int j, const cplx<T>* __restrict__ abk, T ba, T bb,
+                                               T scale) {
+  using C = cplx<T>;
+  constexpr int R = FftShape<NT>::R, TPS = NT / R;
+  constexpr int NU = R / 2 + 1;
+#pragma unroll 2
+  for (int u = 0; u < NU; ++u) {
+    const int k = j + u * TPS;
+    if (k > NT / 2 || (u == R / 2 && j != 0)) continue;
+    const int kp = (NT - k) & (NT - 1);
+    const C zk = my[k * S], zp = my[kp * S];
+    const C A = abk[2 * k], Bk = abk[2 * k + 1];
+    const C Ma = inv_sqrt_principal<T>(C{A.x + ba * Bk.x, A.y + ba * Bk.y});
+    const C Mb = inv_sqrt_principal<T>(C{A.x + bb * Bk.x, A.y + bb * Bk.y});
+    const C sp = cscale(cadd(Ma, Mb), scale), sm = cscale(csub(Ma, Mb), scale);
+    my[k * S] = cadd(cmul(sp, zk), cmul(sm, cconj(zp)));
+    if (kp != k) my[kp * S] = cadd(cmul(cconj(sp), zp), cmul(cconj(sm), cconj(zk)));
+  }
+}
+
 template <typename T, int NT>
 __global__ void __launch_bounds__(block_threads<NT>())
 k_time(DevPlan P, int check) {
@@ -253,8 +230,8 @@ k_time(DevPlan P, int check) {
   const C* __restrict__ abk = reinterpret_cast<const C*>(P.abk);
   const C* __restrict__ tw = reinterpret_cast<const C*>(P.twt);
   const T* __restrict__ beta = reinterpret_cast<const T*>(P.beta);
-  const T ba = valid ? beta[2 * pair] : (T)0;
-  const T bb = valid ? beta[2 * pair + 1] : (T)0;
+  const T ba = valid ? beta[2 * pair] : (T)1;
+  const T bb = valid ? beta[2 * pair + 1] : (T)1;
   C* my = lds + s;
   C v[R];
   // Y then D: e_t = a^t g_{nt-1-t}
@@ -268,25 +245,13 @@ k_time(DevPlan P, int check) {
 #pragma unroll 1
   for (int rep = 0; rep < 2; ++rep) {
     fft_seq<T, NT, false>(v, j, my, S, tw);
-    // packed spectrum Z_k of the two modes; apply mu^{-1/2} per mode:
-    // Z'_k = ((Ma + Mb) Z_k + (Ma - Mb) conj(Z_{nt-k})) / 2, with the 1/nt of F^{-1}
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < R; ++i) my[(j + i * TPS) * S] = v[i];
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int k = j + i * TPS;
-      const int kp = (NT - k) & (NT - 1);
-      const C zp = cconj(my[kp * S]);
-      const C A = abk[2 * k], Bk = abk[2 * k + 1];
-      const C Ma = inv_sqrt_principal<T>(C{A.x + ba * Bk.x, A.y + ba * Bk.y});
-      const C Mb = inv_sqrt_principal<T>(C{A.x + bb * Bk.x, A.y + bb * Bk.y});
-      const C o = cadd(cmul(cadd(Ma, Mb), v[i]), cmul(csub(Ma, Mb), zp));
-      v[i] = cscale(o, half_inv_n);
-    }
+    spectral_pairs<T, NT>(my, S, j, abk, ba, bb, half_inv_n);
     __syncthreads();
-    fft_seq<T, NT, true>(v, j, my, S, tw);
+    fft_seq<T, NT, true, true>(v, j, my, S, tw);
     if (rep == 0) {
       // D^{-1}, then Y, then D:  h_t = a^{2t-nt+1} c_{nt-1-t}
       __syncthreads();
@@ -325,7 +290,7 @@ k_dstx_inv(DevPlan P, int mode, double* __restrict__ outp) {
   const size_t off = (size_t)b * P.N;
   double* out = outp ? outp + off : nullptr;
   const double* q = nullptr;
-  MinresState* st = P.st + b;
+  const MinresState* st = P.st + b;
   if (mode != INV_PLAIN) {
     if (st->state != ST_RUNNING) return;
     if (mode == INV_GAMMA_INIT) {
@@ -385,12 +350,7 @@ k_dstx_inv(DevPlan P, int mode, double* __restrict__ outp) {
   }
   if (mode == INV_PLAIN) return;
   const double bs = block_sum(acc);
-  const int nblk = gridDim.x;
-  if (!arrive_last(P, b, blockIdx.x, nblk, bs)) return;
-  const double tot = finish_sum(P, b, nblk);
-  if (threadIdx.x != 0) return;
-  if (mode == INV_GAMMA_INIT) finalize_gamma_init(st, tot);
-  else finalize_gamma_iter(st, tot);
+  if (threadIdx.x == 0) part_slot(P, PART_GAMMA, b)[blockIdx.x] = bs;
 }
 
 template <typename T, int L>

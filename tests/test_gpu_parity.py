@@ -224,3 +224,21 @@ def test_async_interface_matches_solve():
     it2, rr2, st2 = p.finish()
     assert it1 == it2 and st1 == st2
     assert torch.equal(u1, u2)
+
+
+def test_plan_reuse_matches_fresh_plans():
+    """Solving twice on one plan gives the same results as two fresh plans (regression:
+    state snapshots of an earlier solve must not end a later one)."""
+    nx, nt, alpha = 63, 64, 1e-2
+    g = Grid(nx, 0, nt)
+    fs = []
+    for seed in (51, 52):
+        src, psi0, psi1 = synth.random_source(nx, 0, nt, seed=seed)
+        fs.append(_dev(aao.build_rhs(g, src, psi0, psi1)[None]))
+    p = _plan(nx, 0, nt, alpha=alpha)
+    first = [p.solve(f, tol=1e-8, maxit=200) for f in fs]
+    for f, (u, it, rr, st) in zip(fs, first):
+        q = _plan(nx, 0, nt, alpha=alpha)
+        u2, it2, rr2, st2 = q.solve(f, tol=1e-8, maxit=200)
+        assert it == it2 and st == st2 == [0]
+        assert torch.equal(u, u2)
