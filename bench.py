@@ -31,6 +31,7 @@ WORKLOADS = {
     "wave2d_511x511x512": dict(nx=511, ny=511, nt=512, alpha=1e-3, batch=1, source="gaussian_field"),
     "batch64_wave2d_127x127x128": dict(nx=127, ny=127, nt=128, alpha=1e-3, batch=64, source="jacobi"),
     "wave1d_63x64": dict(nx=63, ny=0, nt=64, alpha=1e-3, batch=1, source="manufactured1d"),
+    "serving_mix": dict(nx=0, ny=0, nt=0, alpha=0.0, batch=1, source="serving"),
 }
 KERNEL_CLASSES = ["stencil", "dstx_fwd", "dsty", "time", "dstx_inv", "update", "residual", "init", "rhs", "fin"]
 
@@ -61,8 +62,8 @@ def make_inputs(w):
 
 
 def algorithmic_bytes(w, prec, iters_total, solves):
-    """Algorithmic HBM bytes of every kernel class over `solves` solves that took
-    `iters_total` MINRES iterations in total (summed over right-hand sides).
+    """Algorithmic HBM bytes of every kernel class over `solves` right-hand-side solves
+    that took `iters_total` MINRES iterations in total (summed over right-hand sides).
 
     Per right-hand side, with N unknowns, NS = nt*(nx+1)*max(ny,1) scratch values of
     s bytes (8 for FP64, 4 for FP32 transforms):
@@ -114,6 +115,9 @@ def source_sha():
 
 
 def run_gpu(w, prec, steps, warmup, tol, maxit, profile=True):
+    """Time `steps` whole solves (production path: graph-replayed iterations, no
+    per-kernel events), then, if `profile`, repeat the same steps with every kernel
+    bracketed by HIP events on the plan stream to get per-kernel durations."""
     import torch
     from paper_2306_03574_amd import Plan
     dev = torch.device("cuda:0")
@@ -129,24 +133,26 @@ def run_gpu(w, prec, steps, warmup, tol, maxit, profile=True):
         plan.build_rhs(d_src, d_p0, d_p1, f)
         plan.solve(f, u, tol=tol, maxit=maxit)
     torch.cuda.synchronize()
+
+    def timed(n):
+        lat, iters_total, last = [], 0, None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n):
+            ts = time.perf_counter()
+            plan.build_rhs(d_src, d_p0, d_p1, f)
+            last = plan.solve(f, u, tol=tol, maxit=maxit)
+            lat.append(time.perf_counter() - ts)
+            iters_total += sum(last[1])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, lat, iters_total, last
+
+    elapsed, lat, iters_total, last = timed(steps)
+    prof, prof_elapsed, prof_iters = {}, None, None
     if profile:
         plan.profile(True)
         plan.profile_reset()
-    lat = []
-    iters_total = 0
-    last = None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(steps):
-        ts = time.perf_counter()
-        plan.build_rhs(d_src, d_p0, d_p1, f)
-        last = plan.solve(f, u, tol=tol, maxit=maxit)
-        lat.append(time.perf_counter() - ts)
-        iters_total += sum(last[1])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = {}
-    if profile:
+        prof_elapsed, _, prof_iters, _ = timed(steps)
         for k in KERNEL_CLASSES:
             ms, n = plan.profile_read(k)
             prof[k] = {"ms": ms, "launches": n}
@@ -154,7 +160,7 @@ def run_gpu(w, prec, steps, warmup, tol, maxit, profile=True):
     _, iters, relres, status = last
     u_host = u.cpu().numpy()
     return dict(elapsed=elapsed, lat=lat, iters=iters, relres=relres, status=status, iters_total=iters_total,
-                prof=prof, u=u_host)
+                prof=prof, prof_elapsed=prof_elapsed, prof_iters=prof_iters, u=u_host)
 
 
 def cpu_baseline(w, tol, maxit):
@@ -176,6 +182,44 @@ def cpu_baseline(w, tol, maxit):
                        f"{wall:.1f} s wall, {os.cpu_count()} host cores visible)", iters=res.iters, x=res.x)
 
 
+def run_serving(args):
+    """Poisson arrivals of mixed solves through the native server (FP32 transforms,
+    FP64 Krylov): completed solves/s and p50/p99 latency from arrival to result."""
+    from paper_2306_03574_amd.serve import run_trace
+    import synth
+    budget = int(args.budget_gb * (1 << 30))
+    prec = args.prec or "fp32"
+    # warm every shape class once (plans, workspaces and graphs are cached by the server)
+    classes = sorted({(nx, ny, nt, a) for (nx, ny) in synth.workloads.SERVING_SHAPES for nt in synth.workloads.SERVING_NT
+                      for a in synth.workloads.SERVING_ALPHA})
+    log(f"serving: rate {args.rate}/s, {args.requests} requests, budget {args.budget_gb} GB, max_active {args.max_active}")
+    out = None
+    trace = synth.serving_trace(args.rate, args.requests, seed=5)
+    results, wall = run_trace(trace, budget, max_active=args.max_active, prec=prec, tol=args.tol, maxit=args.maxit,
+                              progress=log, warm_classes=classes)
+    lat = np.array([r["latency"] for r in results]) * 1e3
+    ok = sum(1 for r in results if r["status"] == 0 and r["relres"] <= args.tol)
+    per_class = {}
+    for tr, r in zip(trace, results):
+        k = f"{'2d' if tr['ny'] else '1d'}_{tr['nx']}_nt{tr['nt']}"
+        per_class.setdefault(k, []).append(r["latency"] * 1e3)
+    out = {
+        "metric": METRIC, "value": round(len(results) / wall, 3), "unit": "solves/s", "n_gpus": 1,
+        "steps": len(results), "warmup": len(classes), "ms_per_step": round(wall / len(results) * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64-krylov/f32-transforms"
+        if prec == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": "serving_mix", "rate_per_s": args.rate, "requests": len(results),
+                   "budget_gb": args.budget_gb, "max_active": args.max_active, "tol": args.tol,
+                   "precond_precision": prec},
+        "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+        "converged": ok,
+        "per_class_p50_p99_ms": {k: [round(float(np.percentile(v, 50)), 2), round(float(np.percentile(v, 99)), 2),
+                                     len(v)] for k, v in sorted(per_class.items())},
+        "mean_iters": round(float(np.mean([r["iters"] for r in results])), 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,11 +231,18 @@ def main():
     ap.add_argument("--maxit", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision comparison leg")
+    ap.add_argument("--rate", type=float, default=50.0, help="serving: Poisson arrival rate (req/s)")
+    ap.add_argument("--requests", type=int, default=200, help="serving: requests in the trace")
+    ap.add_argument("--budget-gb", type=float, default=160.0, help="serving: HBM budget")
+    ap.add_argument("--max-active", type=int, default=16, help="serving: concurrent solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the solver is single-GPU; see DESIGN.md for "
               "how it would shard). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serving_mix":
+        run_serving(args)
+        return
     w = WORKLOADS[args.workload]
     prec = args.prec or ("fp32" if args.workload == "wave2d_511x511x512" else "fp64")
     other = "fp32" if prec == "fp64" else "fp64"
@@ -207,14 +258,16 @@ def main():
     # roofline of the dominant kernel class over the timed region
     prof = main_run["prof"]
     dom = max((k for k in prof if prof[k]["launches"] > 0), key=lambda k: prof[k]["ms"])
-    abytes = algorithmic_bytes(w, prec, main_run["iters_total"], args.steps)
+    abytes = algorithmic_bytes(w, prec, main_run["prof_iters"], args.steps * B)
     launches = prof[dom]["launches"]
     avg_s = prof[dom]["ms"] / 1e3 / launches
     bytes_per_launch = abytes.get(dom, 0) / launches
     achieved = bytes_per_launch / avg_s / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(dom, args.workload, prec),
-                "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": int(bytes_per_launch)}
+                "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                "timing": "HIP events around every launch on the plan stream, over a second pass of the same "
+                          f"{args.steps} solves ({args.steps / main_run['prof_elapsed']:.2f} solves/s with events on)"}
     kernel_table = {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
                         "GB/s": round(abytes[k] / (v["ms"] / 1e3) / 1e9, 1) if k in abytes and v["ms"] > 0 else None}
                     for k, v in prof.items() if v["launches"]}

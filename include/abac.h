@@ -137,6 +137,52 @@ abac_status abac_profile_enable(abac_plan *plan, int on);
 abac_status abac_profile_read(abac_plan *plan, int kernel, double *total_ms, long long *launches);
 abac_status abac_profile_reset(abac_plan *plan);
 
+/* Fill out[0..n) (DEVICE pointer) with i.i.d. N(0,1) values from the counter-based
+ * Philox4x32-10 generator keyed by `seed` (element e: counter e/4; the four words
+ * become two Box-Muller pairs), on `stream`.  Used for seeded synthetic sources. */
+abac_status abac_fill_normal(void *stream, double *out, size_t n, unsigned long long seed);
+
+/* ---------------------------------------------------------------------------
+ * Request server (continuous batching).  Requests of any supported shape are queued,
+ * admitted while their device memory (plan workspace + right-hand side + solution)
+ * fits an HBM byte budget and a cap on concurrent solves, and advanced one MINRES
+ * iteration at a time on their own HIP streams, so solves admitted at different
+ * times overlap on the device.  Finished solves free their slot at once; plans and
+ * buffers of idle slots are cached per shape and evicted (least recently used) when
+ * a new request needs the memory.  A request's source is i.i.d. N(0,1)
+ * (abac_fill_normal with its seed) with zero initial data.  Not thread-safe.
+ * ------------------------------------------------------------------------- */
+typedef struct abac_server abac_server;
+
+abac_status abac_server_create(size_t budget_bytes, int max_active, abac_server **out);
+abac_status abac_server_destroy(abac_server *server);
+
+/* Queue a solve of grid (nx, ny, nt), final time T, alpha, preconditioner precision
+ * prec, to relative residual tol within maxit iterations.  arrival_s is the arrival
+ * time on the server clock (abac_server_clock); latency is measured from it.  With
+ * keep_solution != 0 the solution stays on the device until abac_server_result
+ * copies it out.  ABAC_EBUDGET if the request can never fit the budget. */
+abac_status abac_server_submit(abac_server *server, int nx, int ny, int nt, double T, double alpha, int prec,
+                               unsigned long long seed, double tol, int maxit, double arrival_s, int keep_solution,
+                               long long *ticket);
+
+/* Make progress without blocking: admit what fits, queue iterations, retire finished
+ * solves.  *active / *queued (may be NULL) receive the current counts. */
+abac_status abac_server_step(abac_server *server, int *active, int *queued);
+
+/* ABAC_EAGAIN while the request is pending.  Otherwise fills iters, relres, status,
+ * latency_s (arrival to observed completion) and, if u_host != NULL and the request
+ * kept its solution, copies the N solution values to host memory; then forgets the
+ * ticket.  Any pointer argument may be NULL. */
+abac_status abac_server_result(abac_server *server, long long ticket, double *u_host, int *iters, double *relres,
+                               int *status, double *latency_s);
+
+/* Seconds since the server was created. */
+double abac_server_clock(abac_server *server);
+
+/* Device bytes currently held by the server (active and cached idle slots). */
+size_t abac_server_bytes_in_use(abac_server *server);
+
 /* Constant string for a status code. */
 const char *abac_status_string(int status);
 

@@ -24,7 +24,9 @@ EXPORTED = [
     "abac_workspace_bytes", "abac_plan_create", "abac_plan_destroy", "abac_build_rhs", "abac_apply_A",
     "abac_apply_Pinv", "abac_minres_solve", "abac_minres_begin", "abac_minres_advance", "abac_minres_poll",
     "abac_minres_finish", "abac_profile_enable", "abac_profile_read", "abac_profile_reset",
-    "abac_status_string", "abac_last_error",
+    "abac_status_string", "abac_last_error", "abac_fill_normal", "abac_server_create", "abac_server_destroy",
+    "abac_server_submit", "abac_server_step", "abac_server_result", "abac_server_clock",
+    "abac_server_bytes_in_use",
 ]
 
 _lib = None
@@ -77,6 +79,24 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abac_status_string.restype = ctypes.c_char_p
     lib.abac_last_error.argtypes = []
     lib.abac_last_error.restype = ctypes.c_char_p
+    LL, ULL = ctypes.c_longlong, ctypes.c_ulonglong
+    lib.abac_fill_normal.argtypes = [VP, VP, SZ, ULL]
+    lib.abac_fill_normal.restype = I
+    lib.abac_server_create.argtypes = [SZ, I, ctypes.POINTER(P)]
+    lib.abac_server_create.restype = I
+    lib.abac_server_destroy.argtypes = [P]
+    lib.abac_server_destroy.restype = I
+    lib.abac_server_submit.argtypes = [P, I, I, I, D, D, I, ULL, D, I, D, I, ctypes.POINTER(LL)]
+    lib.abac_server_submit.restype = I
+    lib.abac_server_step.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I)]
+    lib.abac_server_step.restype = I
+    lib.abac_server_result.argtypes = [P, LL, VP, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(I),
+                                       ctypes.POINTER(D)]
+    lib.abac_server_result.restype = I
+    lib.abac_server_clock.argtypes = [P]
+    lib.abac_server_clock.restype = D
+    lib.abac_server_bytes_in_use.argtypes = [P]
+    lib.abac_server_bytes_in_use.restype = SZ
     _lib = lib
     return lib
 
@@ -87,6 +107,16 @@ def _check(status: int, what: str, ok=(OK,)):
         raise AbacError(status, f"{what}: {lib.abac_status_string(status).decode()} "
                                 f"({lib.abac_last_error().decode()})")
     return status
+
+
+def fill_normal(out: torch.Tensor, seed: int, stream=None):
+    """Fill a float64 device tensor with the library's seeded Philox N(0,1) values."""
+    if out.device.type != "cuda" or out.dtype != torch.float64 or not out.is_contiguous():
+        raise TypeError("out must be a contiguous float64 GPU tensor")
+    s = stream if stream is not None else torch.cuda.current_stream(out.device)
+    _check(load_library().abac_fill_normal(ctypes.c_void_p(s.cuda_stream), ctypes.c_void_p(out.data_ptr()),
+                                           out.numel(), seed), "abac_fill_normal")
+    return out
 
 
 def workspace_bytes(nx: int, ny: int, nt: int, prec: str = "fp64", batch: int = 1) -> int:

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -12,6 +13,7 @@
 
 #include "../../include/abac.h"
 #include "abac_internal.h"
+#include "plan_internal.h"
 
 using namespace abac;
 
@@ -108,38 +110,8 @@ Layout make_layout(const DevPlan& P, int prec) {
   return Lo;
 }
 
-struct ProfPair {
-  int kid;
-  hipEvent_t e0, e1;
-};
-
-constexpr int kRing = 16;
-
 }  // namespace
 
-struct abac_plan {
-  DevPlan P;
-  int prec;
-  double T, alpha;
-  hipStream_t stream;
-  void* ws;
-  size_t ws_bytes;
-  bool own_ws;
-  // asynchronous solve bookkeeping
-  MinresState* h_ring;   // pinned, kRing * B states
-  hipEvent_t ring_ev[kRing];
-  long long ring_posted;  // number of state snapshots enqueued
-  long long ring_base;    // first snapshot of the current solve
-  const double* f;
-  double* u;
-  bool active;
-  // kernel timing
-  bool prof;
-  std::vector<ProfPair> pending;
-  std::vector<hipEvent_t> event_pool;
-  double prof_ms[ABAC_K_COUNT];
-  long long prof_n[ABAC_K_COUNT];
-};
 
 namespace {
 
@@ -217,12 +189,38 @@ abac_status enqueue_iteration(abac_plan* p) {
   return ABAC_OK;
 }
 
-abac_status post_snapshot(abac_plan* p) {
-  const int slot = (int)(p->ring_posted % kRing);
-  HIP_TRY(hipMemcpyAsync(p->h_ring + (size_t)slot * p->P.B, p->P.st, sizeof(MinresState) * p->P.B,
-                         hipMemcpyDeviceToHost, p->stream));
+// The set-up and every iteration end with a kernel that copies the per-RHS state
+// into the host-mapped ring; this event marks when that copy is complete.
+abac_status record_snapshot_event(abac_plan* p) {
+  const int slot = (int)(p->ring_posted % kSnapRing);
   HIP_TRY(hipEventRecord(p->ring_ev[slot], p->stream));
   p->ring_posted++;
+  return ABAC_OK;
+}
+
+abac_status launch_iteration(abac_plan* p) {
+  if (p->prof || !p->use_graph) return enqueue_iteration(p);
+  if (!p->iter_graph || p->graph_f != p->f || p->graph_u != p->u) {
+    if (p->iter_graph) {
+      HIP_TRY(hipGraphExecDestroy(p->iter_graph));
+      p->iter_graph = nullptr;
+    }
+    hipStream_t user = p->stream;
+    p->stream = p->cap_stream;
+    HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
+    abac_status s = enqueue_iteration(p);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    p->stream = user;
+    if (s != ABAC_OK) return s;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&p->iter_graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    p->graph_f = p->f;
+    p->graph_u = p->u;
+  }
+  HIP_TRY(hipGraphLaunch(p->iter_graph, p->stream));
   return ABAC_OK;
 }
 
@@ -244,6 +242,24 @@ void fill_results(const MinresState* s, int B, int* iters, double* relres, int* 
 }
 
 }  // namespace
+
+namespace abac {
+
+abac_status plan_peek_snapshot(abac_plan* p, long long seq, int* ready, const MinresState** states) {
+  *ready = 0;
+  if (seq < 0 || seq >= p->ring_posted || seq < p->ring_posted - kSnapRing) return ABAC_OK;
+  const int slot = (int)(seq % kSnapRing);
+  hipError_t e = hipEventQuery(p->ring_ev[slot]);
+  if (e == hipErrorNotReady) return ABAC_OK;
+  if (e != hipSuccess) return hip_fail(e, "hipEventQuery");
+  *ready = 1;
+  *states = p->h_ring + (size_t)slot * p->P.B;
+  return ABAC_OK;
+}
+
+long long plan_snapshots_posted(const abac_plan* p) { return p->ring_posted; }
+
+}  // namespace abac
 
 extern "C" {
 
@@ -394,15 +410,28 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
   p->ws_bytes = Lo.total;
   p->own_ws = own;
   p->h_ring = nullptr;
-  e = hipHostMalloc(reinterpret_cast<void**>(&p->h_ring), sizeof(MinresState) * (size_t)kRing * batch, hipHostMallocDefault);
-  for (int i = 0; e == hipSuccess && i < kRing; ++i) e = hipEventCreateWithFlags(&p->ring_ev[i], hipEventDisableTiming);
+  p->cap_stream = nullptr;
+  p->iter_graph = nullptr;
+  p->graph_f = nullptr;
+  p->graph_u = nullptr;
+  {
+    const char* env = std::getenv("ABAC_GRAPH");
+    p->use_graph = !(env && env[0] == '0');
+  }
+  e = hipHostMalloc(reinterpret_cast<void**>(&p->h_ring), sizeof(MinresState) * (size_t)kSnapRing * batch,
+                    hipHostMallocMapped);
+  if (e == hipSuccess) {
+    std::memset(p->h_ring, 0, sizeof(MinresState) * (size_t)kSnapRing * batch);
+    e = hipHostGetDevicePointer(reinterpret_cast<void**>(&p->P.host_ring), p->h_ring, 0);
+  }
+  for (int i = 0; e == hipSuccess && i < kSnapRing; ++i) e = hipEventCreateWithFlags(&p->ring_ev[i], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     if (own) (void)hipFree(ws);
     delete p;
     return hip_fail(e, "host ring");
   }
   p->ring_posted = 0;
-  p->ring_base = 0;
   p->f = nullptr;
   p->u = nullptr;
   p->active = false;
@@ -420,7 +449,9 @@ abac_status abac_plan_destroy(abac_plan* p) {
   (void)hipStreamSynchronize(p->stream);
   flush_prof(p);
   for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
-  for (int i = 0; i < kRing; ++i) (void)hipEventDestroy(p->ring_ev[i]);
+  for (int i = 0; i < kSnapRing; ++i) (void)hipEventDestroy(p->ring_ev[i]);
+  if (p->iter_graph) (void)hipGraphExecDestroy(p->iter_graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->h_ring) (void)hipHostFree(p->h_ring);
   if (p->own_ws) (void)hipFree(p->ws);
   delete p;
@@ -452,20 +483,22 @@ abac_status abac_minres_begin(abac_plan* p, const double* f, double* u, double t
   p->f = f;
   p->u = u;
   p->active = true;
-  p->ring_base = p->ring_posted;
+  p->ring_posted = 0;
   RUN(ABAC_K_INIT, launch_init(p->P, f, u, tol, maxit, p->stream));
-  abac_status s = enqueue_pinv(p, nullptr, nullptr, 1);
+  abac_status s = enqueue_pinv(p, nullptr, nullptr, 1);   // ends with the set-up snapshot
   if (s != ABAC_OK) return s;
-  return post_snapshot(p);
+  return record_snapshot_event(p);
 }
 
 abac_status abac_minres_advance(abac_plan* p, int iterations) {
   if (!p || !p->active) return fail(ABAC_EINVAL, "no solve in progress");
   for (int i = 0; i < iterations; ++i) {
-    abac_status s = enqueue_iteration(p);
+    abac_status s = launch_iteration(p);
+    if (s != ABAC_OK) return s;
+    s = record_snapshot_event(p);
     if (s != ABAC_OK) return s;
   }
-  return post_snapshot(p);
+  return ABAC_OK;
 }
 
 abac_status abac_minres_poll(abac_plan* p, int* done) {
@@ -475,9 +508,9 @@ abac_status abac_minres_poll(abac_plan* p, int* done) {
     *done = 1;
     return ABAC_OK;
   }
-  // newest completed snapshot
-  for (long long k = p->ring_posted - 1; k >= p->ring_base && k >= p->ring_posted - kRing; --k) {
-    const int slot = (int)(k % kRing);
+  // newest completed snapshot of this solve
+  for (long long k = p->ring_posted - 1; k >= 0 && k >= p->ring_posted - kSnapRing; --k) {
+    const int slot = (int)(k % kSnapRing);
     hipError_t e = hipEventQuery(p->ring_ev[slot]);
     if (e == hipSuccess) {
       *done = all_stopped(p->h_ring + (size_t)slot * p->P.B, p->P.B) ? 1 : 0;
@@ -490,11 +523,22 @@ abac_status abac_minres_poll(abac_plan* p, int* done) {
 
 abac_status abac_minres_finish(abac_plan* p, int* iters, double* relres, int* status) {
   if (!p || !p->active) return fail(ABAC_EINVAL, "no solve in progress");
-  RUN(ABAC_K_RESIDUAL, launch_stencil(p->P, STENCIL_REPORT, p->u, nullptr, p->f, p->stream));
-  RUN(ABAC_K_FIN, launch_fin(p->P, FIN_REPORT, 0.0, 0, p->stream));
   std::vector<MinresState> h(p->P.B);
   HIP_TRY(hipMemcpyAsync(h.data(), p->P.st, sizeof(MinresState) * p->P.B, hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
+  // The explicit residual of the final iterate is already known for right-hand sides
+  // stopped by the convergence test or maxit; recompute it otherwise.
+  bool report = false;
+  for (int b = 0; b < p->P.B; ++b)
+    if (h[b].state != ST_DONE || (h[b].status != ABAC_OK && h[b].status != ABAC_ENOTCONV) ||
+        (h[b].status == ABAC_OK && h[b].iter > 0 && h[b].res2 > h[b].tol2 * h[b].bnorm2))
+      report = true;
+  if (report) {
+    RUN(ABAC_K_RESIDUAL, launch_stencil(p->P, STENCIL_REPORT, p->u, nullptr, p->f, p->stream));
+    RUN(ABAC_K_FIN, launch_fin(p->P, FIN_REPORT, 0.0, 0, p->stream));
+    HIP_TRY(hipMemcpyAsync(h.data(), p->P.st, sizeof(MinresState) * p->P.B, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+  }
   p->active = false;
   abac_status worst;
   fill_results(h.data(), p->P.B, iters, relres, status, &worst);
@@ -525,7 +569,7 @@ abac_status abac_minres_solve(abac_plan* p, const double* f, double* u, double t
       est = enq + 1;   // prediction was early: take one more step
       continue;
     }
-    const int slot = (int)((p->ring_base + obs + 1) % kRing);
+    const int slot = (int)((obs + 1) % kSnapRing);
     HIP_TRY(hipEventSynchronize(p->ring_ev[slot]));
     ++obs;
     const MinresState* snap = p->h_ring + (size_t)slot * B;

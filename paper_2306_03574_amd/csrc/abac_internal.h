@@ -11,6 +11,7 @@ namespace abac {
 // the MINRES recurrence lives here; kernels read what they need at entry and the
 // last block of a reduction writes the new values.
 enum : int { ST_IDLE = 0, ST_RUNNING = 1, ST_DONE = 2 };
+constexpr int kSnapRing = 16;   // host snapshot slots per right-hand side
 
 struct MinresState {
   double gamma;     // gamma_j, current Lanczos off-diagonal
@@ -34,7 +35,7 @@ struct MinresState {
   int explicit_mode;
   int need_check;   // set by the residual kernel: confirm convergence explicitly
   int lucky;        // gamma_{j+1} == 0: the Krylov space is invariant
-  int pad0;
+  int snap;         // sequence number of the next host snapshot
 };
 
 // Everything a kernel needs about a plan, passed by value.
@@ -66,6 +67,7 @@ struct DevPlan {
   MinresState* st;     // B entries
   double* partials;    // PART_KINDS * B * maxparts
   unsigned* counters;  // B entries
+  MinresState* host_ring;  // device view of the host-mapped snapshot ring (kSnapRing * B)
   int maxparts;
   int pad2_;
 };

@@ -12,7 +12,6 @@ namespace abac {
 
 namespace {
 
-constexpr int kResidualGrid = 256;  // blocks of the (usually idle) explicit residual check
 constexpr int kVecThreads = 256;
 constexpr int kVecPerThread = 16;
 constexpr int kVecMaxBlocks = 1024;
@@ -239,12 +238,24 @@ __device__ void step_gamma_iter(MinresState* st, double g2) {
   if (gn == 0.0) st->lucky = 1;
 }
 
+// Copy the state of right-hand side b into the next slot of the host-mapped ring
+// (zero-copy: the host reads it after an event recorded behind this kernel).
+__device__ __forceinline__ void post_snapshot(const DevPlan& P, int b) {
+  MinresState* st = P.st + b;
+  const int seq = st->snap;
+  if (P.host_ring) P.host_ring[(size_t)(seq % kSnapRing) * P.B + b] = *st;
+  st->snap = seq + 1;
+}
+
 __global__ void __launch_bounds__(kVecThreads)
 k_fin(DevPlan P, int kind, int nparts, double tol, int maxit) {
   const int b = blockIdx.x;
   MinresState* st = P.st + b;
-  if (kind != FIN_BNORM && kind != FIN_REPORT && st->state != ST_RUNNING) return;
-  if (kind == FIN_RES && !st->need_check) return;
+  const bool posts = kind == FIN_GAMMA_INIT || kind == FIN_RES;   // end of set-up / of an iteration
+  if ((kind != FIN_BNORM && kind != FIN_REPORT && st->state != ST_RUNNING) || (kind == FIN_RES && !st->need_check)) {
+    if (posts && threadIdx.x == 0) post_snapshot(P, b);
+    return;
+  }
   int pk = PART_RES;
   switch (kind) {
     case FIN_BNORM: pk = PART_RNORM; break;
@@ -264,6 +275,7 @@ k_fin(DevPlan P, int kind, int nparts, double tol, int maxit) {
       st->explicit_mode = 0;
       st->need_check = 0;
       st->lucky = 0;
+      st->snap = 0;
       st->rnorm2 = tot;
       st->res2 = tot;
       st->status = 0;
@@ -316,14 +328,14 @@ k_fin(DevPlan P, int kind, int nparts, double tol, int maxit) {
       st->res2 = tot;
       break;
   }
+  if (posts) post_snapshot(P, b);
 }
 
 }  // namespace
 
 int stencil_grid(const DevPlan& P, int mode) {
-  const int n = stencil_blocks(P);
-  if (mode == STENCIL_RESIDUAL || mode == STENCIL_REPORT) return n < kResidualGrid ? n : kResidualGrid;
-  return n;
+  (void)mode;
+  return stencil_blocks(P);
 }
 
 int update_blocks(const DevPlan& P) {
