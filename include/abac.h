@@ -48,8 +48,10 @@ typedef enum {
 
 typedef enum {
   ABAC_PREC_FP64 = 0,    /* every transform of the preconditioner in FP64             */
-  ABAC_PREC_FP32 = 1     /* preconditioner transforms in FP32 complex; the Krylov
+  ABAC_PREC_FP32 = 1,    /* preconditioner transforms in FP32 complex; the Krylov
                             recurrences, inner products and residual stay FP64        */
+  ABAC_PREC_NONE = 2     /* no preconditioner (P = I): plain MINRES, the comparison
+                            solver "MINRES-I" of Section 3; alpha is ignored           */
 } abac_prec;
 
 /* Bytes of device workspace a plan with these parameters needs (0 if invalid).
@@ -68,6 +70,13 @@ size_t abac_workspace_bytes(int nx, int ny, int nt, int prec, int batch);
  * Host-synchronous with respect to its table upload.  *out is set on success. */
 abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int prec, int batch,
                              void *stream, void *workspace, size_t workspace_bytes, abac_plan **out);
+
+/* Workgroup sizes (threads) the plan's autotuner chose for its transform kernels:
+ * wg[0] first x-DST pass, wg[1] y-DST pass, wg[2] time pass, wg[3] last x-DST pass.
+ * The tuner times every legal tile on the plan's own buffers at creation and caches
+ * the choice per shape (ABAC_TUNE=0 keeps 256-thread defaults; ABAC_TUNE_FILE names
+ * an optional cache file). */
+abac_status abac_plan_tiles(abac_plan *plan, int *wg);
 
 /* Release the plan (synchronises its stream; frees library-owned memory only). */
 abac_status abac_plan_destroy(abac_plan *plan);

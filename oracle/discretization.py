@@ -81,9 +81,10 @@ def laplacian(g: Grid) -> sp.csr_matrix:
     return (sp.kron(sp.identity(g.ny), Dx) + sp.kron(Dy, sp.identity(g.nx))).tocsr()
 
 
-def L_matrix(g: Grid) -> sp.csr_matrix:
-    """L = I_m - (tau^2/2) Delta_h, the diagonal block of T in eq. (1.2)."""
-    return (sp.identity(g.m) - 0.5 * g.tau ** 2 * laplacian(g)).tocsr()
+def L_matrix(g: Grid, abar: float = 1.0) -> sp.csr_matrix:
+    """L = I_m - (tau^2/2) Delta_h, the diagonal block of T in eq. (1.2); with abar,
+    the mean-coefficient block L_abar = I_m - (abar tau^2/2) Delta_h of eq. (3.3)."""
+    return (sp.identity(g.m) - 0.5 * abar * g.tau ** 2 * laplacian(g)).tocsr()
 
 
 def neg_laplacian_eigenvalues(g: Grid) -> np.ndarray:
@@ -102,9 +103,10 @@ def neg_laplacian_eigenvalues(g: Grid) -> np.ndarray:
     return ky[:, None] + kx[None, :]
 
 
-def L_eigenvalues(g: Grid) -> np.ndarray:
-    """lambda_j(L) = 1 + (tau^2/2) kappa_j, shaped like one level."""
-    return 1.0 + 0.5 * g.tau ** 2 * neg_laplacian_eigenvalues(g)
+def L_eigenvalues(g: Grid, abar: float = 1.0) -> np.ndarray:
+    """lambda_j(L) = 1 + (abar tau^2/2) kappa_j, shaped like one level (abar = 1: eq.
+    (1.2); otherwise the mean-coefficient block of eq. (3.3))."""
+    return 1.0 + 0.5 * abar * g.tau ** 2 * neg_laplacian_eigenvalues(g)
 
 
 def dst_space(v: np.ndarray, g: Grid) -> np.ndarray:

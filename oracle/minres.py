@@ -175,3 +175,46 @@ def krylov_minimiser(A: np.ndarray, Pinv: np.ndarray, b: np.ndarray, k: int) -> 
     rhs = C.T @ b
     y, *_ = np.linalg.lstsq(G, rhs, rcond=None)
     return K @ y
+
+
+def exact_minres_count(apply_A, b: np.ndarray, tol: float, kmax: int):
+    """The exact-arithmetic MINRES (x_0 = 0, no preconditioner) iteration count: the
+    smallest k with min over x in K_k(A, b) of ||b - A x||_2 <= tol ||b||_2.  Builds an
+    orthonormal basis of K_k by Arnoldi with two Gram-Schmidt passes (no loss of
+    orthogonality, unlike the three-term recurrence); the least-squares residual of the
+    Hessenberg problem comes from its QR factorisation by Givens rotations, updated one
+    column at a time.  Returns None if kmax steps do not suffice.  Finite-precision
+    MINRES needs about this many steps or more; the delay beyond it comes from the loss
+    of orthogonality of the short recurrence."""
+    b = np.asarray(b, dtype=np.float64).reshape(-1)
+    n = b.size
+    beta = float(np.linalg.norm(b))
+    if beta == 0.0:
+        return 0
+    Q = np.zeros((n, kmax + 1))
+    Q[:, 0] = b / beta
+    cs, sn = [], []
+    g = beta                      # last entry of Q_k^T beta e_1 (the residual norm)
+    for k in range(kmax):
+        v = np.asarray(apply_A(Q[:, k]), dtype=np.float64).reshape(-1).copy()
+        h = np.zeros(k + 2)
+        for _ in range(2):
+            hh = Q[:, :k + 1].T @ v
+            v -= Q[:, :k + 1] @ hh
+            h[:k + 1] += hh
+        h[k + 1] = np.linalg.norm(v)
+        for i in range(k):        # earlier rotations on the new column
+            t = cs[i] * h[i] + sn[i] * h[i + 1]
+            h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1]
+            h[i] = t
+        r = math.hypot(h[k], h[k + 1])
+        c, s = (h[k] / r, h[k + 1] / r) if r > 0.0 else (1.0, 0.0)
+        cs.append(c)
+        sn.append(s)
+        g = -s * g
+        if abs(g) <= tol * beta:
+            return k + 1
+        if h[k + 1] == 0.0:
+            return None
+        Q[:, k + 1] = v / h[k + 1]
+    return None

@@ -44,9 +44,10 @@ def alpha_circulant_factors(nt: int, alpha: float):
     return B1.tocsr(), Za
 
 
-def assemble_C(g: Grid, alpha: float) -> sp.csr_matrix:
-    """C_alpha = B1 (x) L + B2 (x) (-2 I_m), eqs. (1.5)-(1.6) (sparse)."""
-    L = L_matrix(g)
+def assemble_C(g: Grid, alpha: float, abar: float = 1.0) -> sp.csr_matrix:
+    """C_alpha = B1 (x) L + B2 (x) (-2 I_m), eqs. (1.5)-(1.6) (sparse); with abar the
+    blocks are L_abar (eq. (3.3))."""
+    L = L_matrix(g, abar)
     B1, B2 = alpha_circulant_factors(g.nt, alpha)
     return (sp.kron(B1, L) + sp.kron(B2, -2.0 * sp.identity(g.m))).tocsr()
 
@@ -65,11 +66,11 @@ def time_eigenvalues(nt: int, alpha: float):
     return 1.0 + a * a * w * w, -2.0 * a * w
 
 
-def mu_table(g: Grid, alpha: float) -> np.ndarray:
+def mu_table(g: Grid, alpha: float, abar: float = 1.0) -> np.ndarray:
     """Eigenvalues mu_{k,j} = lambda_j(L) lambda_{1,k} + lambda_{2,k} of C_alpha
     (eq. (1.7); Appendix A), shaped [nt] + level_shape."""
     l1, l2 = time_eigenvalues(g.nt, alpha)
-    lam = L_eigenvalues(g)
+    lam = L_eigenvalues(g, abar)
     expand = (slice(None),) + (None,) * lam.ndim
     return lam[None, ...] * l1[expand] + l2[expand]
 
@@ -94,11 +95,11 @@ def time_scaling(nt: int, alpha: float) -> np.ndarray:
 # dense tier
 # --------------------------------------------------------------------------
 
-def dense_sqrt_C(g: Grid, alpha: float) -> np.ndarray:
+def dense_sqrt_C(g: Grid, alpha: float, abar: float = 1.0) -> np.ndarray:
     """C_alpha^{1/2} by scipy.linalg.sqrtm (Schur method, principal branch).
     Lemma on C_alpha in Section 2.1: the result is real; the imaginary part is
     checked small and dropped."""
-    C = assemble_C(g, alpha).toarray()
+    C = assemble_C(g, alpha, abar).toarray()
     S = sla.sqrtm(C)
     S = np.asarray(S)
     if np.iscomplexobj(S):
@@ -108,9 +109,9 @@ def dense_sqrt_C(g: Grid, alpha: float) -> np.ndarray:
     return S
 
 
-def dense_P(g: Grid, alpha: float) -> np.ndarray:
+def dense_P(g: Grid, alpha: float, abar: float = 1.0) -> np.ndarray:
     """P_alpha = (C_alpha^{1/2})^T C_alpha^{1/2} (eq. (1.9)), dense."""
-    S = dense_sqrt_C(g, alpha)
+    S = dense_sqrt_C(g, alpha, abar)
     return S.T @ S
 
 
@@ -129,7 +130,7 @@ def _time_axis_scale(v: np.ndarray, s: np.ndarray) -> np.ndarray:
     return v * s.reshape((-1,) + (1,) * (v.ndim - 1))
 
 
-def apply_C_inv_sqrt_T(g: Grid, alpha: float, y: np.ndarray) -> np.ndarray:
+def apply_C_inv_sqrt_T(g: Grid, alpha: float, y: np.ndarray, abar: float = 1.0) -> np.ndarray:
     """(C_alpha^{-1/2})^T y.
 
     With C_alpha = (D^{-1} F^{-1} (x) S) diag(mu) (F D (x) S) (S = DST-I, F = DFT),
@@ -139,7 +140,7 @@ def apply_C_inv_sqrt_T(g: Grid, alpha: float, y: np.ndarray) -> np.ndarray:
       Step 3: DFT in time, D in time, DST in space.
     Returns a complex array whose imaginary part is rounding noise."""
     d = time_scaling(g.nt, alpha)
-    M = principal_inv_sqrt(mu_table(g, alpha))
+    M = principal_inv_sqrt(mu_table(g, alpha, abar))
     v = dst_space(np.asarray(y, dtype=np.float64), g)
     v = _time_axis_scale(v, 1.0 / d)
     v = np.fft.ifft(v, axis=0)
@@ -149,14 +150,14 @@ def apply_C_inv_sqrt_T(g: Grid, alpha: float, y: np.ndarray) -> np.ndarray:
     return dst_space(v.real, g) + 1j * dst_space(v.imag, g)
 
 
-def apply_C_inv_sqrt(g: Grid, alpha: float, y: np.ndarray) -> np.ndarray:
+def apply_C_inv_sqrt(g: Grid, alpha: float, y: np.ndarray, abar: float = 1.0) -> np.ndarray:
     """C_alpha^{-1/2} y = (D^{-1} F^{-1} (x) S) diag(mu^{-1/2}) (F D (x) S) y:
       Step 1: DST in space, D in time, DFT in time;
       Step 2: multiply by mu^{-1/2};
       Step 3: inverse DFT in time, D^{-1} in time, DST in space.
     Accepts and returns complex arrays."""
     d = time_scaling(g.nt, alpha)
-    M = principal_inv_sqrt(mu_table(g, alpha))
+    M = principal_inv_sqrt(mu_table(g, alpha, abar))
     y = np.asarray(y)
     v = dst_space(y.real, g) + 1j * dst_space(y.imag, g)
     v = _time_axis_scale(v, d)
@@ -167,13 +168,13 @@ def apply_C_inv_sqrt(g: Grid, alpha: float, y: np.ndarray) -> np.ndarray:
     return dst_space(v.real, g) + 1j * dst_space(v.imag, g)
 
 
-def apply_Pinv(g: Grid, alpha: float, y: np.ndarray, check_imag: bool = True) -> np.ndarray:
+def apply_Pinv(g: Grid, alpha: float, y: np.ndarray, check_imag: bool = True, abar: float = 1.0) -> np.ndarray:
     """z = P_alpha^{-1} y = C_alpha^{-1/2} (C_alpha^{-1/2})^T y (Section 2.3).
 
     The result is real (Lemma on C_alpha in Section 2.1); with ``check_imag`` the
     imaginary part is asserted to be rounding noise relative to the real part."""
-    w = apply_C_inv_sqrt_T(g, alpha, y)
-    z = apply_C_inv_sqrt(g, alpha, w)
+    w = apply_C_inv_sqrt_T(g, alpha, y, abar)
+    z = apply_C_inv_sqrt(g, alpha, w, abar)
     if check_imag:
         scale = max(np.max(np.abs(z.real)), 1e-300)
         imag = np.max(np.abs(z.imag))

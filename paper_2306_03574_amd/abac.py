@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libabac.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, EBUDGET, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7
-PREC = {"fp64": 0, "fp32": 1}
+PREC = {"fp64": 0, "fp32": 1, "none": 2}
 KERNELS = {"stencil": 0, "dstx_fwd": 1, "dsty": 2, "time": 3, "dstx_inv": 4, "update": 5,
            "residual": 6, "init": 7, "rhs": 8, "fin": 9}
 
@@ -26,7 +26,7 @@ EXPORTED = [
     "abac_minres_finish", "abac_profile_enable", "abac_profile_read", "abac_profile_reset",
     "abac_status_string", "abac_last_error", "abac_fill_normal", "abac_server_create", "abac_server_destroy",
     "abac_server_submit", "abac_server_step", "abac_server_result", "abac_server_clock",
-    "abac_server_bytes_in_use",
+    "abac_server_bytes_in_use", "abac_plan_tiles",
 ]
 
 _lib = None
@@ -95,6 +95,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abac_server_result.restype = I
     lib.abac_server_clock.argtypes = [P]
     lib.abac_server_clock.restype = D
+    lib.abac_plan_tiles.argtypes = [P, ctypes.POINTER(I)]
+    lib.abac_plan_tiles.restype = I
     lib.abac_server_bytes_in_use.argtypes = [P]
     lib.abac_server_bytes_in_use.restype = SZ
     _lib = lib
@@ -223,6 +225,12 @@ class Plan:
                ok=(OK, ENOTCONV, EBREAKDOWN))
         self._f = None
         return list(iters), list(relres), list(status)
+
+    def tiles(self):
+        """Autotuned workgroup sizes: dict(dstx_fwd, dsty, time, dstx_inv)."""
+        wg = (ctypes.c_int * 4)()
+        _check(self._lib.abac_plan_tiles(self._h, wg), "abac_plan_tiles")
+        return {"dstx_fwd": wg[0], "dsty": wg[1], "time": wg[2], "dstx_inv": wg[3]}
 
     # -- kernel timing -----------------------------------------------------------
     def profile(self, on: bool = True):

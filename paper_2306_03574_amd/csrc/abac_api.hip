@@ -3,6 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <climits>
 #include <cstdlib>
 #include <cmath>
@@ -40,13 +44,22 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+const int kTileCandidates[] = {64, 128, 256, 512, 1024};
+
+int default_wg(int L, int prec, int maxlds) {
+  for (int wg : {256, 512, 1024, 128, 64})
+    if (transform_tile_valid(L, wg, prec) && transform_lds_bytes(L, wg, prec) + 8192 <= (size_t)maxlds) return wg;
+  return 0;
+}
+
 struct Layout {
   size_t twx, twy, twt, beta, abk, sc, sci, scratch, vec[8], st, partials, counters, total;
 };
 
 // Validate the problem and fill the size fields of a DevPlan.
 abac_status describe(int nx, int ny, int nt, double T, double alpha, int prec, int batch, DevPlan& P) {
-  if (prec != ABAC_PREC_FP64 && prec != ABAC_PREC_FP32) return fail(ABAC_EINVAL, "prec must be 0 (FP64) or 1 (FP32)");
+  if (prec != ABAC_PREC_FP64 && prec != ABAC_PREC_FP32 && prec != ABAC_PREC_NONE)
+    return fail(ABAC_EINVAL, "prec must be 0 (FP64), 1 (FP32) or 2 (no preconditioner)");
   if (batch < 1) return fail(ABAC_EINVAL, "batch must be >= 1");
   if (!(T > 0) || !std::isfinite(T)) return fail(ABAC_EINVAL, "T must be positive and finite");
   if (!(alpha > 0) || !(alpha <= 1)) return fail(ABAC_EINVAL, "alpha must be in (0, 1]");
@@ -83,14 +96,19 @@ abac_status describe(int nx, int ny, int nt, double T, double alpha, int prec, i
     P.cy = 0.5 * tau * tau / (hy * hy);
     P.c0 += 2.0 * P.cy;
   }
-  P.maxparts = std::max(stencil_blocks(P), std::max(update_blocks(P), dstx_blocks(P, prec)));
+  // matvec time chunk: the longest of 32/16/8 levels that still gives >= 2048 blocks
+  // (a fixed rule per shape, since the chunk also fixes the grouping of <A z, z>)
+  P.st_chunk = 32;
+  while (P.st_chunk > 8 && (long long)stencil_blocks(P) * P.B < 2048) P.st_chunk /= 2;
+  P.maxparts = std::max(stencil_blocks(P), std::max(update_blocks(P), (P.nt * P.ny1 + 1) / 2));
   P.maxparts = (P.maxparts + 63) & ~63;
+  P.prec = prec;
   return ABAC_OK;
 }
 
 Layout make_layout(const DevPlan& P, int prec) {
   Layout Lo{};
-  const size_t real = prec ? sizeof(float) : sizeof(double);
+  const size_t real = prec == ABAC_PREC_FP32 ? sizeof(float) : sizeof(double);
   const size_t cplx = 2 * real;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
@@ -101,7 +119,7 @@ Layout make_layout(const DevPlan& P, int prec) {
   Lo.abk = take(cplx * 2 * P.nt);
   Lo.sc = take(real * P.nt);
   Lo.sci = take(real * P.nt);
-  Lo.scratch = take(real * (size_t)P.NS * P.B);
+  Lo.scratch = take(prec == ABAC_PREC_NONE ? 0 : real * (size_t)P.NS * P.B);
   for (int i = 0; i < 8; ++i) Lo.vec[i] = take(sizeof(double) * (size_t)P.N * P.B);
   Lo.st = take(sizeof(MinresState) * P.B);
   Lo.partials = take(sizeof(double) * (size_t)P.maxparts * P.B * PART_KINDS);
@@ -164,6 +182,12 @@ abac_status flush_prof(abac_plan* p) {
 // pass writes Z and finishes the scalar update.
 abac_status enqueue_pinv(abac_plan* p, const double* r, double* z, int minres_mode) {
   const DevPlan& P = p->P;
+  if (p->prec == ABAC_PREC_NONE) {
+    const int mode = minres_mode == 0 ? INV_PLAIN : (minres_mode == 1 ? INV_GAMMA_INIT : INV_GAMMA_ITER);
+    RUN(ABAC_K_DSTX_INV, launch_identity(P, mode, r, z, p->stream));
+    if (minres_mode) RUN(ABAC_K_FIN, launch_fin(P, minres_mode == 1 ? FIN_GAMMA_INIT : FIN_GAMMA_ITER, 0.0, 0, p->stream));
+    return ABAC_OK;
+  }
   const int check = minres_mode != 0;
   const int fwd_mode = minres_mode == 2 ? FWD_LANCZOS : FWD_PLAIN;
   const double* in = minres_mode == 1 ? P.V[1] : r;
@@ -241,6 +265,122 @@ void fill_results(const MinresState* s, int B, int* iters, double* relres, int* 
   }
 }
 
+
+struct TuneKey {
+  int prec, nx, ny, nt, batch;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(prec, nx, ny, nt, batch) < std::tie(o.prec, o.nx, o.ny, o.nt, o.batch);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::array<int, 4>> g_tune;
+bool g_tune_loaded = false;
+
+void tune_file_load() {
+  const char* path = std::getenv("ABAC_TUNE_FILE");
+  g_tune_loaded = true;
+  if (!path) return;
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return;
+  TuneKey k;
+  std::array<int, 4> v;
+  while (std::fscanf(fp, "%d %d %d %d %d %d %d %d %d", &k.prec, &k.nx, &k.ny, &k.nt, &k.batch, &v[0], &v[1], &v[2],
+                     &v[3]) == 9)
+    g_tune[k] = v;
+  std::fclose(fp);
+}
+
+void tune_file_save() {
+  const char* path = std::getenv("ABAC_TUNE_FILE");
+  if (!path) return;
+  FILE* fp = std::fopen(path, "w");
+  if (!fp) return;
+  for (auto& kv : g_tune)
+    std::fprintf(fp, "%d %d %d %d %d %d %d %d %d\n", kv.first.prec, kv.first.nx, kv.first.ny, kv.first.nt,
+                 kv.first.batch, kv.second[0], kv.second[1], kv.second[2], kv.second[3]);
+  std::fclose(fp);
+}
+
+// Time one launcher: one warm-up launch, then the mean of three.
+template <typename F>
+float time_launches(hipStream_t s, F&& launch) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return 1e30f;
+  if (hipEventCreate(&e1) != hipSuccess) return 1e30f;
+  float ms = 1e30f;
+  if (launch() == hipSuccess && hipEventRecord(e0, s) == hipSuccess) {
+    bool ok = true;
+    for (int i = 0; i < 3 && ok; ++i) ok = launch() == hipSuccess;
+    if (ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess)
+      (void)hipEventElapsedTime(&ms, e0, e1);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+
+// Autotuner of the transform tiles: for the first x pass, the y pass and the time
+// pass, every legal workgroup size (64..1024 threads, LDS within the device limit) is
+// timed on the plan's own scratch and buffers in the mode MINRES runs; the fastest is
+// kept.  Results are cached per shape (and in
+// ABAC_TUNE_FILE if set).  ABAC_TUNE=0 keeps the defaults.
+abac_status autotune(DevPlan& P, int prec, hipStream_t s, int maxlds) {
+  const char* env = std::getenv("ABAC_TUNE");
+  if (env && env[0] == '0') return ABAC_OK;
+  const TuneKey key{prec, P.nx, P.ny, P.nt, P.B};
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    if (!g_tune_loaded) tune_file_load();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      P.wg_x = it->second[0];
+      P.wg_xi = it->second[1];
+      P.wg_y = it->second[2];
+      P.wg_t = it->second[3];
+      return ABAC_OK;
+    }
+  }
+  // run the fused MINRES variants on the workspace: a temporary running state with
+  // unit scales (cleared again below) lets the Lanczos and <q, p> paths execute
+  for (int i = 0; i < 3; ++i) HIP_TRY(hipMemsetAsync(P.V[i], 0, sizeof(double) * (size_t)P.N * P.B, s));
+  {
+    std::vector<MinresState> tmp(P.B);
+    std::memset(tmp.data(), 0, sizeof(MinresState) * P.B);
+    for (auto& t : tmp) {
+      t.state = ST_RUNNING;
+      t.sig = 1.0;
+    }
+    HIP_TRY(hipMemcpyAsync(P.st, tmp.data(), sizeof(MinresState) * P.B, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  auto pick = [&](int L, int* field, auto launch) {
+    int best = *field;
+    float best_ms = 1e30f;
+    for (int wg : kTileCandidates) {
+      if (!transform_tile_valid(L, wg, prec) || transform_lds_bytes(L, wg, prec) + 8192 > (size_t)maxlds) continue;
+      *field = wg;
+      const float ms = time_launches(s, launch);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = wg;
+      }
+    }
+    *field = best;
+  };
+  pick(2 * P.Mx, &P.wg_x, [&] { return launch_dstx_fwd(P, prec, FWD_LANCZOS, 1, nullptr, s); });
+  if (P.ny) pick(2 * P.My, &P.wg_y, [&] { return launch_dsty(P, prec, 1, s); });
+  pick(P.nt, &P.wg_t, [&] { return launch_time(P, prec, 1, s); });
+  // the last pass carries the <q, P^{-1} q> reduction: its tile stays at the fixed
+  // default so the summation order (and the iterates) never depend on timing noise
+  HIP_TRY(hipMemsetAsync(P.st, 0, sizeof(MinresState) * P.B, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  (void)hipGetLastError();
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[key] = {P.wg_x, P.wg_xi, P.wg_y, P.wg_t};
+  tune_file_save();
+  return ABAC_OK;
+}
+
 }  // namespace
 
 namespace abac {
@@ -277,15 +417,22 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
   DevPlan P;
   abac_status s = describe(nx, ny, nt, T, alpha, prec, batch, P);
   if (s != ABAC_OK) return s;
-  // LDS limit of the device for the largest transform block
+  // default tiles: 256 threads where the length allows it, within the device LDS limit
   int dev = 0, maxlds = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  const size_t need = std::max(transform_lds_bytes(2 * P.Mx, prec),
-                               std::max(transform_lds_bytes(nt, prec), ny ? transform_lds_bytes(2 * P.My, prec) : 0));
-  if (need + 1024 > (size_t)maxlds)
-    return fail(ABAC_EINVAL, "transform needs " + std::to_string(need) + " B of LDS, device allows " +
-                                 std::to_string(maxlds) + " (use the FP32 preconditioner for this size)");
+  P.wg_x = default_wg(2 * P.Mx, prec, maxlds);
+  // the last pass carries a reduction, so its tile follows a fixed rule (not timing):
+  // the smallest legal tile, which keeps its LDS small and its occupancy high
+  P.wg_xi = 0;
+  for (int wg : kTileCandidates)
+    if (!P.wg_xi && transform_tile_valid(2 * P.Mx, wg, prec) && transform_lds_bytes(2 * P.Mx, wg, prec) + 8192 <= (size_t)maxlds)
+      P.wg_xi = wg;
+  P.wg_y = ny ? default_wg(2 * P.My, prec, maxlds) : 256;
+  P.wg_t = default_wg(nt, prec, maxlds);
+  if (prec != ABAC_PREC_NONE && (!P.wg_x || !P.wg_xi || !P.wg_y || !P.wg_t))
+    return fail(ABAC_EINVAL, "transform does not fit the device LDS (" + std::to_string(maxlds) +
+                                 " B); use the FP32 preconditioner for this size");
   const Layout Lo = make_layout(P, prec);
   void* ws = workspace;
   bool own = false;
@@ -363,7 +510,7 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
     sc[k] = std::exp(la * k);
     sci[k] = std::exp(-la * k);
   }
-  if (alpha > 0.5) {
+  if (alpha > 0.5 && prec != ABAC_PREC_NONE) {
     // C_alpha can be (nearly) singular as alpha -> 1 (remark on Strang's circulant);
     // reject plans whose spectrum touches zero.
     double mu_max = 0.0;
@@ -381,7 +528,7 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
     }
   }
   auto upload = [&](const void* dst, const std::vector<double>& v) -> hipError_t {
-    if (prec == ABAC_PREC_FP64) return hipMemcpy(const_cast<void*>(dst), v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (prec != ABAC_PREC_FP32) return hipMemcpy(const_cast<void*>(dst), v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
     std::vector<float> f(v.begin(), v.end());
     return hipMemcpy(const_cast<void*>(dst), f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
   };
@@ -395,10 +542,19 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
   if (e == hipSuccess) e = upload(P.sci, sci);
   if (e == hipSuccess) e = hipMemset(P.counters, 0, sizeof(unsigned) * batch);
   if (e == hipSuccess) e = hipMemset(P.st, 0, sizeof(MinresState) * batch);
-  if (e == hipSuccess) e = hipMemset(P.scratch, 0, (prec ? 4 : 8) * (size_t)P.NS * batch);
+  if (e == hipSuccess && prec != ABAC_PREC_NONE)
+    e = hipMemset(P.scratch, 0, (prec ? 4 : 8) * (size_t)P.NS * batch);
   if (e != hipSuccess) {
     if (own) (void)hipFree(ws);
     return hip_fail(e, "table upload");
+  }
+  P.gamma_nparts = prec == ABAC_PREC_NONE ? update_blocks(P) : dstx_blocks(P, P.wg_xi);
+  if (prec != ABAC_PREC_NONE) {
+    abac_status ts = autotune(P, prec, static_cast<hipStream_t>(stream), maxlds);
+    if (ts != ABAC_OK) {
+      if (own) (void)hipFree(ws);
+      return ts;
+    }
   }
   abac_plan* p = new abac_plan();
   p->P = P;
@@ -611,6 +767,15 @@ abac_status abac_profile_reset(abac_plan* p) {
     p->prof_ms[k] = 0;
     p->prof_n[k] = 0;
   }
+  return ABAC_OK;
+}
+
+abac_status abac_plan_tiles(abac_plan* p, int* wg) {
+  if (!p || !wg) return fail(ABAC_EINVAL, "NULL argument");
+  wg[0] = p->P.wg_x;
+  wg[1] = p->P.wg_y;
+  wg[2] = p->P.wg_t;
+  wg[3] = p->P.wg_xi;
   return ABAC_OK;
 }
 

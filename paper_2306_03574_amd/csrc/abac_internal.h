@@ -12,6 +12,7 @@ namespace abac {
 // last block of a reduction writes the new values.
 enum : int { ST_IDLE = 0, ST_RUNNING = 1, ST_DONE = 2 };
 constexpr int kSnapRing = 16;   // host snapshot slots per right-hand side
+constexpr size_t kMaxTransformLds = 128 * 1024;   // dynamic LDS per transform block
 
 struct MinresState {
   double gamma;     // gamma_j, current Lanczos off-diagonal
@@ -69,7 +70,12 @@ struct DevPlan {
   unsigned* counters;  // B entries
   MinresState* host_ring;  // device view of the host-mapped snapshot ring (kSnapRing * B)
   int maxparts;
-  int pad2_;
+  // workgroup sizes of the transform kernels (chosen by the plan's autotuner)
+  int wg_x, wg_xi, wg_y, wg_t;
+  int st_chunk;        // forward time levels per matvec block
+  int gamma_nparts;    // partial sums of <q, P^{-1} q> per right-hand side
+  int prec;            // 0 FP64 transforms, 1 FP32 transforms, 2 no preconditioner
+  int pad3_;
 };
 
 // ---------------------------------------------------------------------------
@@ -101,10 +107,17 @@ __device__ __forceinline__ double block_sum(double v) {
   return s;
 }
 
-// Fixed-order sum of n partials by the whole block; result valid in thread 0.
+// Fixed-order sum of n partials by the whole block (pairs per thread, then the block
+// tree); result valid in thread 0.  `part` is 16-byte aligned.
 __device__ __forceinline__ double sum_parts(const double* __restrict__ part, int n) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  const double2* p2 = reinterpret_cast<const double2*>(part);
+  const int n2 = n >> 1;
+  for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+    const double2 v = p2[i];
+    s += v.x + v.y;
+  }
+  if ((n & 1) && threadIdx.x == 0) s += part[n - 1];
   return block_sum(s);
 }
 
@@ -125,24 +138,26 @@ enum FwdMode : int { FWD_PLAIN = 0, FWD_LANCZOS = 1 };
 enum InvMode : int { INV_PLAIN = 0, INV_GAMMA_INIT = 1, INV_GAMMA_ITER = 2 };
 enum FinKind : int { FIN_BNORM = 0, FIN_DELTA = 1, FIN_GAMMA_INIT = 2, FIN_GAMMA_ITER = 3, FIN_RES = 4, FIN_REPORT = 5 };
 
-// matvec decomposition: 256 spatial points per block, 32 forward time levels (plus
-// their mirrors) per block
+// matvec decomposition: 256 spatial points per block and st_chunk forward time levels
+// (plus their mirrors) per block
 constexpr int kStencilThreads = 256;
-constexpr int kChunk = 32;
 __host__ __device__ inline int stencil_blocks(const DevPlan& P) {
   const int tiles = (P.m + kStencilThreads - 1) / kStencilThreads;
-  const int nchunks = (P.nt / 2 + kChunk - 1) / kChunk;
+  const int nchunks = (P.nt / 2 + P.st_chunk - 1) / P.st_chunk;
   return tiles * nchunks;
 }
 int stencil_grid(const DevPlan& P, int mode);
 int update_blocks(const DevPlan& P);
-int dstx_blocks(const DevPlan& P, int prec);
+int dstx_blocks(const DevPlan& P, int wg);
 
 hipError_t launch_stencil(const DevPlan& P, int mode, const double* x, double* y, const double* f, hipStream_t s);
 hipError_t launch_rhs(const DevPlan& P, const double* src, const double* psi0, const double* psi1, double* f,
                       hipStream_t s);
 hipError_t launch_init(const DevPlan& P, const double* f, double* u, double tol, int maxit, hipStream_t s);
 hipError_t launch_update(const DevPlan& P, double* u, hipStream_t s);
+// identity preconditioner: z = r (mode 0), or the MINRES set-up / Lanczos step with
+// z = q and the partials of <q, q> (modes INV_GAMMA_INIT / INV_GAMMA_ITER)
+hipError_t launch_identity(const DevPlan& P, int mode, const double* in, double* out, hipStream_t s);
 // one block per right-hand side: fixed-order sum of the partials of a reduction and
 // the scalar step that consumes it
 hipError_t launch_fin(const DevPlan& P, int kind, double tol, int maxit, hipStream_t s);
@@ -152,6 +167,8 @@ hipError_t launch_dstx_fwd(const DevPlan& P, int prec, int mode, int check, cons
 hipError_t launch_dsty(const DevPlan& P, int prec, int check, hipStream_t s);
 hipError_t launch_time(const DevPlan& P, int prec, int check, hipStream_t s);
 hipError_t launch_dstx_inv(const DevPlan& P, int prec, int mode, double* out, hipStream_t s);
-size_t transform_lds_bytes(int L, int prec);
+size_t transform_lds_bytes(int L, int wg, int prec);
+bool transform_tile_valid(int L, int wg, int prec);
+int transform_tps(int L);
 
 }  // namespace abac

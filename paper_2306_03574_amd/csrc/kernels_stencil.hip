@@ -38,8 +38,8 @@ __device__ __forceinline__ double stencil_tile(const DevPlan& P, int mode, const
   const int i = tile * kStencilThreads + threadIdx.x;
   if (i >= m) return 0.0;
   const int ix = i % P.nx, iy = i / P.nx;
-  const int k0 = chunk * kChunk;
-  const int k1 = min(k0 + kChunk, n / 2);
+  const int k0 = chunk * P.st_chunk;
+  const int k1 = min(k0 + P.st_chunk, n / 2);
   double acc = 0.0;
   // forward march state: x_{k-1}, x_{k-2} and L of them
   double zf1 = 0.0, zf2 = 0.0, Lf1 = 0.0, Lf2 = 0.0;
@@ -200,6 +200,48 @@ k_update(DevPlan P, double* __restrict__ u) {
   if (threadIdx.x == 0) part_slot(P, PART_RNORM, b)[blockIdx.x] = bs;
 }
 
+// Identity preconditioner (MINRES-I): z = q, with the Lanczos step fused in.
+__global__ void __launch_bounds__(kVecThreads)
+k_identity(DevPlan P, int mode, const double* __restrict__ in, double* __restrict__ out) {
+  const int b = blockIdx.y;
+  const size_t off = (size_t)b * P.N;
+  const int nblk = gridDim.x;
+  const size_t per = ((size_t)P.N + nblk - 1) / nblk;
+  const size_t lo = (size_t)blockIdx.x * per;
+  const size_t hi = lo + per < (size_t)P.N ? lo + per : (size_t)P.N;
+  if (mode == INV_PLAIN) {
+    for (size_t e = lo + threadIdx.x; e < hi; e += blockDim.x) out[off + e] = in[off + e];
+    return;
+  }
+  const MinresState* st = P.st + b;
+  if (st->state != ST_RUNNING) return;
+  double acc = 0.0;
+  if (mode == INV_GAMMA_INIT) {
+    const double* __restrict__ q = P.V[1] + off;
+    double* __restrict__ z = P.Z[1] + off;
+    for (size_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+      const double v = q[e];
+      z[e] = v;
+      acc += v * v;
+    }
+  } else {
+    const int j = st->iter + 1;
+    double* __restrict__ q = P.V[(j + 1) % 3] + off;
+    const double* __restrict__ vj = P.V[j % 3] + off;
+    const double* __restrict__ vjm1 = P.V[(j + 2) % 3] + off;
+    double* __restrict__ z = P.Z[(j + 1) & 1] + off;
+    const double cA = st->sig, cB = st->delta * st->sig, cC = st->gamma * st->sig_prev;
+    for (size_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+      const double v = cA * q[e] - cB * vj[e] - cC * vjm1[e];
+      q[e] = v;
+      z[e] = v;
+      acc += v * v;
+    }
+  }
+  const double bs = block_sum(acc);
+  if (threadIdx.x == 0) part_slot(P, PART_GAMMA, b)[blockIdx.x] = bs;
+}
+
 // Lanczos coefficient gamma_{j+1} and the Givens QR update of iteration j.
 __device__ void step_gamma_iter(MinresState* st, double g2) {
   if (!(g2 >= 0.0) || !(g2 < 1e300)) {
@@ -247,7 +289,9 @@ __device__ __forceinline__ void post_snapshot(const DevPlan& P, int b) {
   st->snap = seq + 1;
 }
 
-__global__ void __launch_bounds__(kVecThreads)
+constexpr int kFinThreads = 1024;
+
+__global__ void __launch_bounds__(kFinThreads)
 k_fin(DevPlan P, int kind, int nparts, double tol, int maxit) {
   const int b = blockIdx.x;
   MinresState* st = P.st + b;
@@ -374,16 +418,22 @@ hipError_t launch_update(const DevPlan& P, double* u, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_identity(const DevPlan& P, int mode, const double* in, double* out, hipStream_t s) {
+  dim3 grid(update_blocks(P), P.B);
+  hipLaunchKernelGGL(k_identity, grid, dim3(kVecThreads), 0, s, P, mode, in, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_fin(const DevPlan& P, int kind, double tol, int maxit, hipStream_t s) {
   int nparts;
   switch (kind) {
     case FIN_BNORM: nparts = update_blocks(P); break;
     case FIN_DELTA: nparts = stencil_grid(P, STENCIL_MINRES); break;
     case FIN_GAMMA_INIT:
-    case FIN_GAMMA_ITER: nparts = dstx_blocks(P, 0); break;
+    case FIN_GAMMA_ITER: nparts = P.gamma_nparts; break;
     default: nparts = stencil_grid(P, STENCIL_RESIDUAL); break;
   }
-  hipLaunchKernelGGL(k_fin, dim3(P.B), dim3(kVecThreads), 0, s, P, kind, nparts, tol, maxit);
+  hipLaunchKernelGGL(k_fin, dim3(P.B), dim3(kFinThreads), 0, s, P, kind, nparts, tol, maxit);
   return hipGetLastError();
 }
 

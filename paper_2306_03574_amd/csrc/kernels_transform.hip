@@ -14,14 +14,23 @@
 //
 // Scratch layout (private to the apply): [batch][nt][ny1][Mx] in the transform
 // precision, Mx = nx+1; column Mx-1 is a zero pad so rows and mode pairs are aligned.
+//
+// Every transform kernel is instantiated for several workgroup sizes WG (tile =
+// WG / TPS sequences per block); the plan's autotuner picks one per kernel.
+#include <algorithm>
+
 #include "abac_internal.h"
 
 namespace abac {
 
 namespace {
 
-template <int L> constexpr int seqs_per_block() { return fft_tps<L>() >= 256 ? 1 : 256 / fft_tps<L>(); }
-template <int L> constexpr int block_threads() { return seqs_per_block<L>() * fft_tps<L>(); }
+template <int L, int WG> constexpr int seqs_of() { return WG / fft_tps<L>(); }
+template <typename T, int L, int WG>
+constexpr bool tile_ok() {
+  return WG >= fft_tps<L>() && WG % fft_tps<L>() == 0 && WG % 64 == 0 &&
+         (size_t)seqs_of<L, WG>() * L * sizeof(cplx<T>) <= kMaxTransformLds;
+}
 
 template <typename T>
 __device__ __forceinline__ cplx<T> inv_sqrt_principal(cplx<T> mu) {
@@ -45,15 +54,34 @@ __device__ __forceinline__ cplx<T> inv_sqrt_principal(cplx<T> mu) {
   return cplx<T>{sr * g, -si * g};
 }
 
+// Copy a [rows][width] tile held in LDS with row stride `ld` to `rows` consecutive
+// global rows of length `width` (one contiguous range), coalesced.
+template <typename TS, typename TD>
+__device__ __forceinline__ void tile_out(TD* __restrict__ dst, const TS* src, int rows, int width, int ld) {
+  const int total = rows * width;
+  int e = threadIdx.x;
+  int r = e / width, c = e - r * width;
+  const int dr = blockDim.x / width, dc = blockDim.x - dr * width;
+  for (; e < total; e += blockDim.x) {
+    dst[e] = (TD)src[r * ld + c];
+    r += dr;
+    c += dc;
+    if (c >= width) {
+      c -= width;
+      ++r;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // first pass: DST-I along x of every row (FP64 in, transform precision out),
 // optionally fused with the Lanczos step q = sig_j A Z_j - delta v_j - gamma_j v_{j-1}
 // ---------------------------------------------------------------------------
-template <typename T, int L>
-__global__ void __launch_bounds__(block_threads<L>())
+template <typename T, int L, int WG>
+__global__ void __launch_bounds__(WG)
 k_dstx_fwd(DevPlan P, int mode, int check, const double* __restrict__ in) {
   using C = cplx<T>;
-  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_per_block<L>(), Mx = L / 2;
+  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_of<L, WG>(), Mx = L / 2;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   T* stage = reinterpret_cast<T*>(smem);
@@ -115,32 +143,35 @@ k_dstx_fwd(DevPlan P, int mode, int check, const double* __restrict__ in) {
   __syncthreads();
   fft_seq<T, L, false>(v, j, lds + s, S, reinterpret_cast<const C*>(P.twx));
   const T scl = (T)(1.0 / sqrt((double)L));
-  T* out = reinterpret_cast<T*>(P.scratch) + (size_t)b * P.NS;
+  // stage the transformed rows ([2S][Mx+1] padded) and write them out contiguously
+  __syncthreads();
+  constexpr int LDO = Mx + 1;
 #pragma unroll
   for (int i = 0; i <= R / 2; ++i) {
     const int k = j + i * TPS;
     if (k == 0 || k > Mx) continue;
-    int col;
-    T oa, ob;
     if (k == Mx) {
-      col = Mx - 1; oa = 0; ob = 0;
+      stage[ra * LDO + Mx - 1] = 0;
+      stage[rb * LDO + Mx - 1] = 0;
     } else {
-      col = k - 1; oa = -v[i].y * scl; ob = v[i].x * scl;
+      stage[ra * LDO + k - 1] = -v[i].y * scl;
+      stage[rb * LDO + k - 1] = v[i].x * scl;
     }
-    if (va) out[(size_t)(row0 + ra) * Mx + col] = oa;
-    if (vb) out[(size_t)(row0 + rb) * Mx + col] = ob;
   }
+  __syncthreads();
+  T* out = reinterpret_cast<T*>(P.scratch) + (size_t)b * P.NS + (size_t)row0 * Mx;
+  tile_out<T, T>(out, stage, nrows, Mx, LDO);
 }
 
 // ---------------------------------------------------------------------------
 // y pass (2D): DST-I along y of every column, in place on the scratch; two adjacent
 // columns form one complex sequence.
 // ---------------------------------------------------------------------------
-template <typename T, int L>
-__global__ void __launch_bounds__(block_threads<L>())
+template <typename T, int L, int WG>
+__global__ void __launch_bounds__(WG)
 k_dsty(DevPlan P, int check) {
   using C = cplx<T>;
-  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_per_block<L>(), My = L / 2;
+  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_of<L, WG>(), My = L / 2;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   const int b = blockIdx.y;
@@ -182,6 +213,7 @@ k_dsty(DevPlan P, int check) {
 // ---------------------------------------------------------------------------
 // time pass: per spatial mode pair, out = K Y K Y g, in place on the scratch.
 // ---------------------------------------------------------------------------
+
 // Spectral weights of two real modes packed as one complex sequence z = g_a + i g_b:
 // with Z = F z, the spectra of the two modes are (Z_k + conj Z_{-k})/2 and
 // (Z_k - conj Z_{-k})/(2i); weighting them by Ma_k, Mb_k and repacking gives
@@ -210,11 +242,11 @@ __device__ __forceinline__ void spectral_pairs(cplx<T>* my, int S, int j, const 
   }
 }
 
-template <typename T, int NT>
-__global__ void __launch_bounds__(block_threads<NT>())
+template <typename T, int NT, int WG>
+__global__ void __launch_bounds__(WG)
 k_time(DevPlan P, int check) {
   using C = cplx<T>;
-  constexpr int R = FftShape<NT>::R, TPS = NT / R, S = seqs_per_block<NT>();
+  constexpr int R = FftShape<NT>::R, TPS = NT / R, S = seqs_of<NT, WG>();
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   const int b = blockIdx.y;
@@ -276,16 +308,17 @@ k_time(DevPlan P, int check) {
 
 // ---------------------------------------------------------------------------
 // last pass: inverse DST-I along x (transform precision in, FP64 out), optionally
-// fused with <q, p> and the MINRES scalar update.
+// fused with the partial sums of <q, p>.
 // ---------------------------------------------------------------------------
-template <typename T, int L>
-__global__ void __launch_bounds__(block_threads<L>())
+template <typename T, int L, int WG>
+__global__ void __launch_bounds__(WG)
 k_dstx_inv(DevPlan P, int mode, double* __restrict__ outp) {
   using C = cplx<T>;
-  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_per_block<L>(), Mx = L / 2;
+  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_of<L, WG>(), Mx = L / 2;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   T* stage = reinterpret_cast<T*>(smem);
+  double* ostage = reinterpret_cast<double*>(smem);
   const int b = blockIdx.y;
   const size_t off = (size_t)b * P.N;
   double* out = outp ? outp + off : nullptr;
@@ -331,21 +364,36 @@ k_dstx_inv(DevPlan P, int mode, double* __restrict__ outp) {
   __syncthreads();
   fft_seq<T, L, false>(v, j, lds + s, S, reinterpret_cast<const C*>(P.twx));
   const double scl = 1.0 / sqrt((double)L);
-  double acc = 0.0;
+  // stage the FP64 rows ([2S][nx+2] padded: odd stride in 8-byte words) and write
+  // them out contiguously; with q, accumulate <q, p> in a fixed order for a fixed tile
+  __syncthreads();
+  const int ldo = nx + 2;
 #pragma unroll
   for (int i = 0; i <= R / 2; ++i) {
     const int k = j + i * TPS;
     if (k == 0 || k >= Mx) continue;
-    const double pa = -(double)v[i].y * scl, pb = (double)v[i].x * scl;
-    const size_t ia = (size_t)(row0 + ra) * nx + (k - 1);
-    const size_t ib = (size_t)(row0 + rb) * nx + (k - 1);
-    if (va) {
-      out[ia] = pa;
-      if (q) acc += pa * q[ia];
-    }
-    if (vb) {
-      out[ib] = pb;
-      if (q) acc += pb * q[ib];
+    ostage[ra * ldo + k - 1] = -(double)v[i].y * scl;
+    ostage[rb * ldo + k - 1] = (double)v[i].x * scl;
+  }
+  __syncthreads();
+  double* o = out + (size_t)row0 * nx;
+  const int total = nrows * nx;
+  double acc = 0.0;
+  {
+    const double* qq = q ? q + (size_t)row0 * nx : nullptr;
+    int e = threadIdx.x;
+    int r = e / nx, c = e - r * nx;
+    const int dr = blockDim.x / nx, dc = blockDim.x - dr * nx;
+    for (; e < total; e += blockDim.x) {
+      const double val = ostage[r * ldo + c];
+      o[e] = val;
+      if (qq) acc += val * qq[e];
+      r += dr;
+      c += dc;
+      if (c >= nx) {
+        c -= nx;
+        ++r;
+      }
     }
   }
   if (mode == INV_PLAIN) return;
@@ -353,109 +401,123 @@ k_dstx_inv(DevPlan P, int mode, double* __restrict__ outp) {
   if (threadIdx.x == 0) part_slot(P, PART_GAMMA, b)[blockIdx.x] = bs;
 }
 
-template <typename T, int L>
+// ---------------------------------------------------------------------------
+// launchers: one instantiation per (precision, length, workgroup size)
+// ---------------------------------------------------------------------------
+template <typename T, int L, int WG>
 hipError_t launch_x_fwd_t(const DevPlan& P, int mode, int check, const double* in, hipStream_t s) {
-  constexpr int S = seqs_per_block<L>();
-  const int rows = P.nt * P.ny1;
-  dim3 grid((rows + 2 * S - 1) / (2 * S), P.B);
-  const size_t lds = (size_t)S * L * sizeof(cplx<T>);
-  hipLaunchKernelGGL((k_dstx_fwd<T, L>), grid, dim3(block_threads<L>()), lds, s, P, mode, check, in);
-  return hipGetLastError();
+  if constexpr (!tile_ok<T, L, WG>()) {
+    return hipErrorInvalidValue;
+  } else {
+    constexpr int S = seqs_of<L, WG>();
+    const int rows = P.nt * P.ny1;
+    dim3 grid((rows + 2 * S - 1) / (2 * S), P.B);
+    const size_t lds = (size_t)S * L * sizeof(cplx<T>);
+    hipLaunchKernelGGL((k_dstx_fwd<T, L, WG>), grid, dim3(WG), lds, s, P, mode, check, in);
+    return hipGetLastError();
+  }
 }
 
-template <typename T, int L>
+template <typename T, int L, int WG>
 hipError_t launch_x_inv_t(const DevPlan& P, int mode, double* out, hipStream_t s) {
-  constexpr int S = seqs_per_block<L>();
-  const int rows = P.nt * P.ny1;
-  dim3 grid((rows + 2 * S - 1) / (2 * S), P.B);
-  const size_t lds = (size_t)S * L * sizeof(cplx<T>);
-  hipLaunchKernelGGL((k_dstx_inv<T, L>), grid, dim3(block_threads<L>()), lds, s, P, mode, out);
-  return hipGetLastError();
+  if constexpr (!tile_ok<T, L, WG>()) {
+    return hipErrorInvalidValue;
+  } else {
+    constexpr int S = seqs_of<L, WG>();
+    const int rows = P.nt * P.ny1;
+    dim3 grid((rows + 2 * S - 1) / (2 * S), P.B);
+    const size_t lds = std::max((size_t)S * L * sizeof(cplx<T>), (size_t)2 * S * (L / 2 + 1) * sizeof(double));
+    hipLaunchKernelGGL((k_dstx_inv<T, L, WG>), grid, dim3(WG), lds, s, P, mode, out);
+    return hipGetLastError();
+  }
 }
 
-template <typename T, int L>
+template <typename T, int L, int WG>
 hipError_t launch_y_t(const DevPlan& P, int check, hipStream_t s) {
-  constexpr int S = seqs_per_block<L>();
-  const int cpairs = P.Mx / 2;
-  const int bpl = (cpairs + S - 1) / S;
-  dim3 grid(bpl * P.nt, P.B);
-  const size_t lds = (size_t)S * L * sizeof(cplx<T>);
-  hipLaunchKernelGGL((k_dsty<T, L>), grid, dim3(block_threads<L>()), lds, s, P, check);
-  return hipGetLastError();
+  if constexpr (!tile_ok<T, L, WG>()) {
+    return hipErrorInvalidValue;
+  } else {
+    constexpr int S = seqs_of<L, WG>();
+    const int cpairs = P.Mx / 2;
+    const int bpl = (cpairs + S - 1) / S;
+    dim3 grid(bpl * P.nt, P.B);
+    const size_t lds = (size_t)S * L * sizeof(cplx<T>);
+    hipLaunchKernelGGL((k_dsty<T, L, WG>), grid, dim3(WG), lds, s, P, check);
+    return hipGetLastError();
+  }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, int WG>
 hipError_t launch_time_t(const DevPlan& P, int check, hipStream_t s) {
-  constexpr int S = seqs_per_block<NT>();
-  const int npairs = P.ms / 2;
-  dim3 grid((npairs + S - 1) / S, P.B);
-  const size_t lds = (size_t)S * NT * sizeof(cplx<T>);
-  hipLaunchKernelGGL((k_time<T, NT>), grid, dim3(block_threads<NT>()), lds, s, P, check);
-  return hipGetLastError();
+  if constexpr (!tile_ok<T, NT, WG>()) {
+    return hipErrorInvalidValue;
+  } else {
+    constexpr int S = seqs_of<NT, WG>();
+    const int npairs = P.ms / 2;
+    dim3 grid((npairs + S - 1) / S, P.B);
+    const size_t lds = (size_t)S * NT * sizeof(cplx<T>);
+    hipLaunchKernelGGL((k_time<T, NT, WG>), grid, dim3(WG), lds, s, P, check);
+    return hipGetLastError();
+  }
 }
 
-#define ABAC_SWITCH_L(LVAR, CALL)                      \
-  switch (LVAR) {                                      \
-    case 16: return CALL(16);                          \
-    case 32: return CALL(32);                          \
-    case 64: return CALL(64);                          \
-    case 128: return CALL(128);                        \
-    case 256: return CALL(256);                        \
-    case 512: return CALL(512);                        \
-    case 1024: return CALL(1024);                      \
-    case 2048: return CALL(2048);                      \
-    case 4096: return CALL(4096);                      \
-    case 8192: return CALL(8192);                      \
-    default: return hipErrorInvalidValue;              \
+#define ABAC_SWITCH_WG(WGVAR, CALL, LL)      \
+  switch (WGVAR) {                           \
+    case 64: return CALL(LL, 64);            \
+    case 128: return CALL(LL, 128);          \
+    case 256: return CALL(LL, 256);          \
+    case 512: return CALL(LL, 512);          \
+    case 1024: return CALL(LL, 1024);        \
+    default: return hipErrorInvalidValue;    \
   }
 
-#define ABAC_SWITCH_NT(LVAR, CALL)                     \
-  switch (LVAR) {                                      \
-    case 8: return CALL(8);                            \
-    case 16: return CALL(16);                          \
-    case 32: return CALL(32);                          \
-    case 64: return CALL(64);                          \
-    case 128: return CALL(128);                        \
-    case 256: return CALL(256);                        \
-    case 512: return CALL(512);                        \
-    case 1024: return CALL(1024);                      \
-    default: return hipErrorInvalidValue;              \
+#define ABAC_SWITCH_L(LVAR, WGVAR, CALL)                                           \
+  switch (LVAR) {                                                                  \
+    case 8: ABAC_SWITCH_WG(WGVAR, CALL, 8)                                         \
+    case 16: ABAC_SWITCH_WG(WGVAR, CALL, 16)                                       \
+    case 32: ABAC_SWITCH_WG(WGVAR, CALL, 32)                                       \
+    case 64: ABAC_SWITCH_WG(WGVAR, CALL, 64)                                       \
+    case 128: ABAC_SWITCH_WG(WGVAR, CALL, 128)                                     \
+    case 256: ABAC_SWITCH_WG(WGVAR, CALL, 256)                                     \
+    case 512: ABAC_SWITCH_WG(WGVAR, CALL, 512)                                     \
+    case 1024: ABAC_SWITCH_WG(WGVAR, CALL, 1024)                                   \
+    case 2048: ABAC_SWITCH_WG(WGVAR, CALL, 2048)                                   \
+    case 4096: ABAC_SWITCH_WG(WGVAR, CALL, 4096)                                   \
+    case 8192: ABAC_SWITCH_WG(WGVAR, CALL, 8192)                                   \
+    default: return hipErrorInvalidValue;                                          \
   }
 
 template <typename T>
 hipError_t x_fwd_dispatch(const DevPlan& P, int mode, int check, const double* in, hipStream_t s) {
-#define CALL(LL) launch_x_fwd_t<T, LL>(P, mode, check, in, s)
-  ABAC_SWITCH_L(2 * P.Mx, CALL)
+#define CALL(LL, WW) launch_x_fwd_t<T, LL, WW>(P, mode, check, in, s)
+  ABAC_SWITCH_L(2 * P.Mx, P.wg_x, CALL)
 #undef CALL
 }
 
 template <typename T>
 hipError_t x_inv_dispatch(const DevPlan& P, int mode, double* out, hipStream_t s) {
-#define CALL(LL) launch_x_inv_t<T, LL>(P, mode, out, s)
-  ABAC_SWITCH_L(2 * P.Mx, CALL)
+#define CALL(LL, WW) launch_x_inv_t<T, LL, WW>(P, mode, out, s)
+  ABAC_SWITCH_L(2 * P.Mx, P.wg_xi, CALL)
 #undef CALL
 }
 
 template <typename T>
 hipError_t y_dispatch(const DevPlan& P, int check, hipStream_t s) {
-#define CALL(LL) launch_y_t<T, LL>(P, check, s)
-  switch (2 * P.My) {
-    case 16: return CALL(16);
-    case 32: return CALL(32);
-    case 64: return CALL(64);
-    case 128: return CALL(128);
-    case 256: return CALL(256);
-    case 512: return CALL(512);
-    case 1024: return CALL(1024);
-    default: return hipErrorInvalidValue;
-  }
+#define CALL(LL, WW) launch_y_t<T, LL, WW>(P, check, s)
+  ABAC_SWITCH_L(2 * P.My, P.wg_y, CALL)
 #undef CALL
 }
 
 template <typename T>
 hipError_t time_dispatch(const DevPlan& P, int check, hipStream_t s) {
-#define CALL(LL) launch_time_t<T, LL>(P, check, s)
-  ABAC_SWITCH_NT(P.nt, CALL)
+#define CALL(LL, WW) launch_time_t<T, LL, WW>(P, check, s)
+  ABAC_SWITCH_L(P.nt, P.wg_t, CALL)
+#undef CALL
+}
+
+template <typename T> hipError_t tile_check_t(int L, int wg) {
+#define CALL(LL, WW) (tile_ok<T, LL, WW>() ? hipSuccess : hipErrorInvalidValue)
+  ABAC_SWITCH_L(L, wg, CALL)
 #undef CALL
 }
 
@@ -477,43 +539,36 @@ hipError_t launch_dstx_inv(const DevPlan& P, int prec, int mode, double* out, hi
   return prec ? x_inv_dispatch<float>(P, mode, out, s) : x_inv_dispatch<double>(P, mode, out, s);
 }
 
-int dstx_blocks(const DevPlan& P, int prec) {
-  (void)prec;
-  int S;
-  switch (2 * P.Mx) {
-    case 16: S = seqs_per_block<16>(); break;
-    case 32: S = seqs_per_block<32>(); break;
-    case 64: S = seqs_per_block<64>(); break;
-    case 128: S = seqs_per_block<128>(); break;
-    case 256: S = seqs_per_block<256>(); break;
-    case 512: S = seqs_per_block<512>(); break;
-    case 1024: S = seqs_per_block<1024>(); break;
-    case 2048: S = seqs_per_block<2048>(); break;
-    case 4096: S = seqs_per_block<4096>(); break;
-    default: S = seqs_per_block<8192>(); break;
+bool transform_tile_valid(int L, int wg, int prec) {
+  return (prec ? tile_check_t<float>(L, wg) : tile_check_t<double>(L, wg)) == hipSuccess;
+}
+
+int transform_tps(int L) {
+  switch (L) {
+    case 8: return fft_tps<8>();
+    case 16: return fft_tps<16>();
+    case 32: return fft_tps<32>();
+    case 64: return fft_tps<64>();
+    case 128: return fft_tps<128>();
+    case 256: return fft_tps<256>();
+    case 512: return fft_tps<512>();
+    case 1024: return fft_tps<1024>();
+    case 2048: return fft_tps<2048>();
+    case 4096: return fft_tps<4096>();
+    case 8192: return fft_tps<8192>();
+    default: return 0;
   }
+}
+
+int dstx_blocks(const DevPlan& P, int wg) {
+  const int S = wg / transform_tps(2 * P.Mx);
   const int rows = P.nt * P.ny1;
   return (rows + 2 * S - 1) / (2 * S);
 }
 
-size_t transform_lds_bytes(int L, int prec) {
+size_t transform_lds_bytes(int L, int wg, int prec) {
   const size_t c = prec ? sizeof(float2) : sizeof(double2);
-  int S;
-  switch (L) {
-    case 8: S = seqs_per_block<8>(); break;
-    case 16: S = seqs_per_block<16>(); break;
-    case 32: S = seqs_per_block<32>(); break;
-    case 64: S = seqs_per_block<64>(); break;
-    case 128: S = seqs_per_block<128>(); break;
-    case 256: S = seqs_per_block<256>(); break;
-    case 512: S = seqs_per_block<512>(); break;
-    case 1024: S = seqs_per_block<1024>(); break;
-    case 2048: S = seqs_per_block<2048>(); break;
-    case 4096: S = seqs_per_block<4096>(); break;
-    case 8192: S = seqs_per_block<8192>(); break;
-    default: return 0;
-  }
-  return (size_t)S * L * c;
+  return (size_t)(wg / transform_tps(L)) * L * c;
 }
 
 }  // namespace abac

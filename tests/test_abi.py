@@ -51,6 +51,7 @@ def test_workspace_bytes_validation(lib, nx, ny, nt, ok):
         N = nt * nx * max(ny, 1)
         assert n >= 8 * 8 * N          # eight FP64 Krylov vectors at least
         assert lib.abac_workspace_bytes(nx, ny, nt, 1, 1) < n   # FP32 scratch is smaller
+        assert lib.abac_workspace_bytes(nx, ny, nt, 2, 1) < lib.abac_workspace_bytes(nx, ny, nt, 1, 1)  # no scratch
         assert lib.abac_workspace_bytes(nx, ny, nt, 0, 4) > 3 * n
 
 
@@ -58,7 +59,7 @@ def test_workspace_bytes_validation(lib, nx, ny, nt, ok):
     (63, 0, 64, 1.0, 0.0, 0, 1),      # alpha = 0
     (63, 0, 64, 1.0, 1.5, 0, 1),      # alpha > 1
     (63, 0, 64, -1.0, 0.1, 0, 1),     # T < 0
-    (63, 0, 64, 1.0, 0.1, 2, 1),      # bad precision
+    (63, 0, 64, 1.0, 0.1, 3, 1),      # bad precision
     (63, 0, 64, 1.0, 0.1, 0, 0),      # batch 0
     (62, 0, 64, 1.0, 0.1, 0, 1),      # nx+1 not a power of two
 ])

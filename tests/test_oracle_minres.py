@@ -142,3 +142,39 @@ def test_closed_form_solve_1d():
     (x,) = g.points()
     u_cf = A * np.sin(np.arange(1, nt + 1) * phi)[:, None] * np.sin(np.pi * x)[None, :]
     assert np.max(np.abs(res.x - u_cf)) < 1e-11
+
+
+def test_exact_count_terminates_at_number_of_distinct_eigenvalues():
+    """Closed form: with d distinct eigenvalues, exact-arithmetic MINRES reaches a zero
+    residual in exactly d steps for a right-hand side touching every eigenspace."""
+    rng = np.random.default_rng(3)
+    lam = np.repeat(np.array([-3.0, -0.5, 0.25, 1.0, 2.0, 7.0]), 9)
+    b = rng.standard_normal(lam.size)
+    assert mr.exact_minres_count(lambda v: lam * v, b, 1e-12, 40) == 6
+    assert mr.exact_minres_count(lambda v: lam * v, b, 1e-12, 5) is None
+
+
+def test_exact_count_matches_brute_force_minimiser():
+    """Brute force: the count is the first k whose Krylov minimiser meets the tolerance."""
+    g = Grid(5, 3, 6)
+    src, psi0, psi1 = synth.random_source(5, 3, 6, seed=23)
+    b = aao.reverse_time(aao.build_rhs(g, src, psi0, psi1)).reshape(-1)
+    A = (aao.assemble_Y(g) @ aao.assemble_T(g)).toarray()
+    I = np.eye(g.N)
+    tol = 1e-3
+    k_exact = mr.exact_minres_count(lambda v: A @ v, b, tol, g.N)
+    brute = next(k for k in range(1, g.N + 1)
+                 if np.linalg.norm(b - A @ mr.krylov_minimiser(A, I, b, k)) <= tol * np.linalg.norm(b))
+    assert k_exact == brute
+
+
+def test_unpreconditioned_count_lies_between_exact_arithmetic_and_printed():
+    """The MINRES-I count of Table 1 (614 at tau = h = 2^-4) is a finite-precision
+    count: exact arithmetic needs fewer steps (the stored count, written from the
+    oracle), and loss of orthogonality of the short recurrence makes up the rest."""
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "exact_minres_counts.json")))
+    g, b, _, L = _example1(4, 4)
+    k_exact = mr.exact_minres_count(lambda v: aao.apply_A(g, v.reshape(g.shape), L), b, 1e-6, 700)
+    assert k_exact == gold["example1"]["4,4"]
+    res = mr.minres(lambda u: aao.apply_A(g, u, L), lambda y: y.copy(), b, tol=1e-6, maxit=5000)
+    assert k_exact < res.iters <= T1[(4, 4)][5]
