@@ -81,11 +81,29 @@ abac_status abac_plan_tiles(abac_plan *plan, int *wg);
 /* Release the plan (synchronises its stream; frees library-owned memory only). */
 abac_status abac_plan_destroy(abac_plan *plan);
 
+/* Variable coefficient of the wave equation u_tt = div(a grad u) + f (Section 3,
+ * eq. (3.1)).  Afterwards the matrix-vector product, the right-hand side and the
+ * explicit residual use L_a = I - (tau^2/2) Delta_{a,h} (eq. (3.2)), the conservative
+ * central difference (a_e (u_e - u) - a_w (u - u_w))/hx^2 + (same in y)/hy^2 with a
+ * taken at the cell faces; the preconditioner is built from the mean-coefficient
+ * matrix with L_abar = I - (abar tau^2/2) Delta_h (eq. (3.3)).
+ *   a_xh:  HOST array [ny1][nx+1] (ny1 = max(ny,1)): a at (x_{i+1/2}, y_j),
+ *          x_{i+1/2} = (i + 1/2) hx for i = 0..nx, y_j = (j+1) hy (row 0 in 1D);
+ *   a_yh:  HOST array [ny+1][nx] (2D only; ignored in 1D): a at (x_i, y_{j+1/2});
+ *   abar:  the preconditioner's constant coefficient (the paper takes the mean of a
+ *          over the grid points), > 0.
+ * a_xh = NULL restores the constant coefficient a = 1 (abar ignored).  Every entry
+ * must be positive and finite (ABAC_EINVAL otherwise, nothing changed).  The face
+ * weights are copied into the workspace; host-synchronous; not allowed while a
+ * solve is in progress (ABAC_EINVAL). */
+abac_status abac_plan_set_coefficient(abac_plan *plan, const double *a_xh, const double *a_yh, double abar);
+
 /* Right-hand side f of eq. (1.2) from source samples src = f^(0..nt-1)
  * ([batch][nt][...]), initial displacement psi0 and velocity psi1 ([batch][...],
  * one level each):  f_1 = tau^2 f^(0)/2 + tau psi1 + psi0,
  * f_2 = tau^2 f^(1) - L psi0,  f_k = tau^2 f^(k-1) for k >= 3,
- * with L = I - (tau^2/2) Laplace_h.  f must not alias the inputs. */
+ * with L = I - (tau^2/2) Laplace_h (L_a with a variable coefficient, eq. (3.2)).
+ * f must not alias the inputs. */
 abac_status abac_build_rhs(abac_plan *plan, const double *src, const double *psi0, const double *psi1,
                            double *f);
 

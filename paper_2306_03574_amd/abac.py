@@ -26,7 +26,7 @@ EXPORTED = [
     "abac_minres_finish", "abac_profile_enable", "abac_profile_read", "abac_profile_reset",
     "abac_status_string", "abac_last_error", "abac_fill_normal", "abac_server_create", "abac_server_destroy",
     "abac_server_submit", "abac_server_step", "abac_server_result", "abac_server_clock",
-    "abac_server_bytes_in_use", "abac_plan_tiles",
+    "abac_server_bytes_in_use", "abac_plan_tiles", "abac_plan_set_coefficient",
 ]
 
 _lib = None
@@ -97,6 +97,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abac_server_clock.restype = D
     lib.abac_plan_tiles.argtypes = [P, ctypes.POINTER(I)]
     lib.abac_plan_tiles.restype = I
+    lib.abac_plan_set_coefficient.argtypes = [P, VP, VP, D]
+    lib.abac_plan_set_coefficient.restype = I
     lib.abac_server_bytes_in_use.argtypes = [P]
     lib.abac_server_bytes_in_use.restype = SZ
     _lib = lib
@@ -225,6 +227,32 @@ class Plan:
                ok=(OK, ENOTCONV, EBREAKDOWN))
         self._f = None
         return list(iters), list(relres), list(status)
+
+    def set_coefficient(self, a_xh=None, a_yh=None, abar: float | None = None):
+        """Variable coefficient a(x) of u_tt = div(a grad u) + f (eq. (3.1)): face values
+        a_xh [ny1][nx+1] at (x_{i+1/2}, y_j) and, in 2D, a_yh [ny+1][nx] at (x_i, y_{j+1/2}),
+        host arrays; abar is the preconditioner's constant coefficient (eq. (3.3)).
+        a_xh=None restores a = 1."""
+        import numpy as np
+        if a_xh is None:
+            _check(self._lib.abac_plan_set_coefficient(self._h, None, None, 1.0), "abac_plan_set_coefficient")
+            return
+        ny1 = self.ny if self.ny else 1
+        ax = np.ascontiguousarray(a_xh, dtype=np.float64)
+        if ax.size != ny1 * (self.nx + 1):
+            raise ValueError(f"a_xh must hold {ny1} x {self.nx + 1} values")
+        ay = None
+        if self.ny:
+            if a_yh is None:
+                raise ValueError("a_yh is required in 2D")
+            ay = np.ascontiguousarray(a_yh, dtype=np.float64)
+            if ay.size != (self.ny + 1) * self.nx:
+                raise ValueError(f"a_yh must hold {self.ny + 1} x {self.nx} values")
+        if abar is None:
+            raise ValueError("abar (the preconditioner's constant coefficient) is required")
+        _check(self._lib.abac_plan_set_coefficient(
+            self._h, ctypes.c_void_p(ax.ctypes.data), ctypes.c_void_p(ay.ctypes.data) if ay is not None else None,
+            float(abar)), "abac_plan_set_coefficient")
 
     def tiles(self):
         """Autotuned workgroup sizes: dict(dstx_fwd, dsty, time, dstx_inv)."""

@@ -53,7 +53,7 @@ int default_wg(int L, int prec, int maxlds) {
 }
 
 struct Layout {
-  size_t twx, twy, twt, beta, abk, sc, sci, scratch, vec[8], st, partials, counters, total;
+  size_t twx, twy, twt, beta, abk, sc, sci, coef, scratch, vec[8], st, partials, counters, total;
 };
 
 // Validate the problem and fill the size fields of a DevPlan.
@@ -119,6 +119,7 @@ Layout make_layout(const DevPlan& P, int prec) {
   Lo.abk = take(cplx * 2 * P.nt);
   Lo.sc = take(real * P.nt);
   Lo.sci = take(real * P.nt);
+  Lo.coef = take(sizeof(double) * ((size_t)P.ny1 * P.Mx + (P.ny ? (size_t)P.My * P.nx : 0)));
   Lo.scratch = take(prec == ABAC_PREC_NONE ? 0 : real * (size_t)P.NS * P.B);
   for (int i = 0; i < 8; ++i) Lo.vec[i] = take(sizeof(double) * (size_t)P.N * P.B);
   Lo.st = take(sizeof(MinresState) * P.B);
@@ -401,6 +402,83 @@ long long plan_snapshots_posted(const abac_plan* p) { return p->ring_posted; }
 
 }  // namespace abac
 
+namespace {
+
+// beta_q = (abar tau^2/2) * eigenvalue of -Laplace_h of scratch mode q in the sine basis,
+// (4/h^2) sin^2(j pi h / 2) summed over the axes (pad column: 1, harmless); the time
+// tables of mu_k(beta) = A_k + beta B_k with A_k = (1 - a w_k)^2, B_k = 1 + a^2 w_k^2,
+// w_k = exp(-2 pi i k/nt), a = alpha^{1/nt}; 1 - a w_k is evaluated without
+// cancellation as ((1-a) + 2 a sin^2(th/2)) + i a sin(th).  D_alpha scalings a^{+-t}.
+void spectral_tables(const DevPlan& P, double alpha, double abar, std::vector<double>& beta,
+                     std::vector<double>& abk, std::vector<double>& sc, std::vector<double>& sci) {
+  const double pi = 3.14159265358979323846;
+  const int nx = P.nx, ny = P.ny, nt = P.nt, Mx = P.Mx;
+  const double hx = 1.0 / Mx, hy = ny ? 1.0 / P.My : 0.0;
+  std::vector<double> kx(nx), ky(ny ? ny : 1, 0.0);
+  for (int j = 0; j < nx; ++j) {
+    const double sj = std::sin((j + 1) * pi * hx / 2.0);
+    kx[j] = 4.0 / (hx * hx) * sj * sj;
+  }
+  for (int j = 0; j < ny; ++j) {
+    const double sj = std::sin((j + 1) * pi * hy / 2.0);
+    ky[j] = 4.0 / (hy * hy) * sj * sj;
+  }
+  beta.assign(P.ms, 1.0);
+  for (int yy = 0; yy < P.ny1; ++yy)
+    for (int xx = 0; xx < nx; ++xx)
+      beta[(size_t)yy * Mx + xx] = 0.5 * abar * P.tau2 * (kx[xx] + (ny ? ky[yy] : 0.0));
+  abk.assign(4 * nt, 0.0);
+  sc.assign(nt, 0.0);
+  sci.assign(nt, 0.0);
+  const double la = std::log(alpha) / nt;
+  const double a = std::exp(la);
+  const double oma = -std::expm1(la);
+  for (int k = 0; k < nt; ++k) {
+    const double th = 2.0 * pi * k / nt;
+    const double sh = std::sin(0.5 * th);
+    const double re = oma + 2.0 * a * sh * sh, im = a * std::sin(th);
+    abk[4 * k + 0] = re * re - im * im;
+    abk[4 * k + 1] = 2.0 * re * im;
+    abk[4 * k + 2] = 1.0 + a * a * std::cos(2.0 * th);
+    abk[4 * k + 3] = -a * a * std::sin(2.0 * th);
+    sc[k] = std::exp(la * k);
+    sci[k] = std::exp(-la * k);
+  }
+}
+
+// C_alpha can be (nearly) singular as alpha -> 1 (the remark on Strang's circulant,
+// Section 2.1); true when the smallest |mu| is below 1e-12 of the largest.
+bool spectrum_near_singular(const DevPlan& P, const std::vector<double>& beta, const std::vector<double>& abk) {
+  double mu_min = 1e300, mu_max = 0.0;
+  for (int k = 0; k < P.nt; ++k)
+    for (size_t q = 0; q < (size_t)P.ms; ++q) {
+      if (q % P.Mx == (size_t)(P.Mx - 1)) continue;
+      const double mr = abk[4 * k] + beta[q] * abk[4 * k + 2], mi = abk[4 * k + 1] + beta[q] * abk[4 * k + 3];
+      const double mag = std::hypot(mr, mi);
+      mu_min = std::min(mu_min, mag);
+      mu_max = std::max(mu_max, mag);
+    }
+  return mu_min <= 1e-12 * mu_max;
+}
+
+// Copy a table to the device in the transform precision, ordered on `stream` and
+// complete on return (the host vector is temporary).
+hipError_t upload_table(void* dst, const std::vector<double>& v, int prec, hipStream_t stream) {
+  std::vector<float> f;
+  const void* src = v.data();
+  size_t bytes = v.size() * sizeof(double);
+  if (prec == ABAC_PREC_FP32) {
+    f.assign(v.begin(), v.end());
+    src = f.data();
+    bytes = f.size() * sizeof(float);
+  }
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  return e;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t abac_workspace_bytes(int nx, int ny, int nt, int prec, int batch) {
@@ -461,6 +539,8 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
   P.st = reinterpret_cast<MinresState*>(base + Lo.st);
   P.partials = reinterpret_cast<double*>(base + Lo.partials);
   P.counters = reinterpret_cast<unsigned*>(base + Lo.counters);
+  P.coef_x = nullptr;   // constant coefficient until abac_plan_set_coefficient
+  P.coef_y = nullptr;
 
   // ---- spectral tables in FP64 --------------------------------------------
   const double pi = 3.14159265358979323846;
@@ -477,55 +557,10 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
   twiddles(twx, 2 * Mx);
   twiddles(twy, 2 * My);
   twiddles(twt, nt);
-  // (tau^2/2) times the eigenvalues of -Laplace_h in the sine basis:
-  // (4/h^2) sin^2(j pi h / 2), summed over the axes; pad column gets 1 (harmless)
-  const double hx = 1.0 / Mx, hy = ny ? 1.0 / My : 0.0;
-  std::vector<double> kx(nx), ky(ny ? ny : 1, 0.0);
-  for (int j = 0; j < nx; ++j) {
-    const double sj = std::sin((j + 1) * pi * hx / 2.0);
-    kx[j] = 4.0 / (hx * hx) * sj * sj;
-  }
-  for (int j = 0; j < ny; ++j) {
-    const double sj = std::sin((j + 1) * pi * hy / 2.0);
-    ky[j] = 4.0 / (hy * hy) * sj * sj;
-  }
-  for (int yy = 0; yy < P.ny1; ++yy)
-    for (int xx = 0; xx < Mx; ++xx)
-      beta[(size_t)yy * Mx + xx] = xx < nx ? 0.5 * P.tau2 * (kx[xx] + (ny ? ky[yy] : 0.0)) : 1.0;
-  // mu_{k}(beta) = A_k + beta B_k with A_k = (1 - a w_k)^2, B_k = 1 + a^2 w_k^2,
-  // w_k = exp(-2 pi i k/nt), a = alpha^{1/nt}; 1 - a w_k evaluated without
-  // cancellation as ((1-a) + 2 a sin^2(th/2)) + i a sin(th).
-  const double la = std::log(alpha) / nt;
-  const double a = std::exp(la);
-  const double oma = -std::expm1(la);
-  double mu_min = 1e300;
-  for (int k = 0; k < nt; ++k) {
-    const double th = 2.0 * pi * k / nt;
-    const double sh = std::sin(0.5 * th);
-    const double re = oma + 2.0 * a * sh * sh, im = a * std::sin(th);
-    abk[4 * k + 0] = re * re - im * im;
-    abk[4 * k + 1] = 2.0 * re * im;
-    abk[4 * k + 2] = 1.0 + a * a * std::cos(2.0 * th);
-    abk[4 * k + 3] = -a * a * std::sin(2.0 * th);
-    sc[k] = std::exp(la * k);
-    sci[k] = std::exp(-la * k);
-  }
-  if (alpha > 0.5 && prec != ABAC_PREC_NONE) {
-    // C_alpha can be (nearly) singular as alpha -> 1 (remark on Strang's circulant);
-    // reject plans whose spectrum touches zero.
-    double mu_max = 0.0;
-    for (int k = 0; k < nt; ++k)
-      for (size_t q = 0; q < (size_t)P.ms; ++q) {
-        if (q % Mx == (size_t)(Mx - 1)) continue;
-        const double mr = abk[4 * k] + beta[q] * abk[4 * k + 2], mi = abk[4 * k + 1] + beta[q] * abk[4 * k + 3];
-        const double mag = std::hypot(mr, mi);
-        mu_min = std::min(mu_min, mag);
-        mu_max = std::max(mu_max, mag);
-      }
-    if (mu_min <= 1e-12 * mu_max) {
-      if (own) (void)hipFree(ws);
-      return fail(ABAC_EINVAL, "C_alpha is numerically singular for this alpha and grid");
-    }
+  spectral_tables(P, alpha, 1.0, beta, abk, sc, sci);
+  if (alpha > 0.5 && prec != ABAC_PREC_NONE && spectrum_near_singular(P, beta, abk)) {
+    if (own) (void)hipFree(ws);
+    return fail(ABAC_EINVAL, "C_alpha is numerically singular for this alpha and grid");
   }
   auto upload = [&](const void* dst, const std::vector<double>& v) -> hipError_t {
     if (prec != ABAC_PREC_FP32) return hipMemcpy(const_cast<void*>(dst), v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
@@ -565,6 +600,8 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
   p->ws = ws;
   p->ws_bytes = Lo.total;
   p->own_ws = own;
+  p->coef_ws = reinterpret_cast<double*>(base + Lo.coef);
+  p->abar = 1.0;
   p->h_ring = nullptr;
   p->cap_stream = nullptr;
   p->iter_graph = nullptr;
@@ -611,6 +648,47 @@ abac_status abac_plan_destroy(abac_plan* p) {
   if (p->h_ring) (void)hipHostFree(p->h_ring);
   if (p->own_ws) (void)hipFree(p->ws);
   delete p;
+  return ABAC_OK;
+}
+
+abac_status abac_plan_set_coefficient(abac_plan* p, const double* a_xh, const double* a_yh, double abar) {
+  g_last_error.clear();
+  if (!p) return fail(ABAC_EINVAL, "plan is NULL");
+  if (p->active) return fail(ABAC_EINVAL, "a solve is in progress on this plan");
+  DevPlan& P = p->P;
+  const size_t nfx = (size_t)P.ny1 * P.Mx, nfy = P.ny ? (size_t)P.My * P.nx : 0;
+  std::vector<double> w(nfx + nfy);
+  if (a_xh) {
+    if (P.ny && !a_yh) return fail(ABAC_EINVAL, "a_yh is required in 2D");
+    if (!(abar > 0) || !std::isfinite(abar)) return fail(ABAC_EINVAL, "abar must be positive and finite");
+    for (size_t i = 0; i < nfx; ++i) {
+      if (!(a_xh[i] > 0) || !std::isfinite(a_xh[i])) return fail(ABAC_EINVAL, "a_xh entries must be positive and finite");
+      w[i] = P.cx * a_xh[i];
+    }
+    for (size_t i = 0; i < nfy; ++i) {
+      if (!(a_yh[i] > 0) || !std::isfinite(a_yh[i])) return fail(ABAC_EINVAL, "a_yh entries must be positive and finite");
+      w[nfx + i] = P.cy * a_yh[i];
+    }
+  } else {
+    abar = 1.0;
+  }
+  std::vector<double> beta, abk, sc, sci;
+  if (p->prec != ABAC_PREC_NONE) {
+    spectral_tables(P, p->alpha, abar, beta, abk, sc, sci);
+    if (p->alpha > 0.5 && spectrum_near_singular(P, beta, abk))
+      return fail(ABAC_EINVAL, "the mean-coefficient C_alpha is numerically singular for this alpha");
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (a_xh) HIP_TRY(upload_table(p->coef_ws, w, ABAC_PREC_FP64, p->stream));
+  if (p->prec != ABAC_PREC_NONE) HIP_TRY(upload_table(const_cast<void*>(P.beta), beta, p->prec, p->stream));
+  P.coef_x = a_xh ? p->coef_ws : nullptr;
+  P.coef_y = a_xh && P.ny ? p->coef_ws + nfx : nullptr;
+  p->abar = abar;
+  // kernels take the plan by value: a captured iteration holds the old coefficients
+  if (p->iter_graph) {
+    HIP_TRY(hipGraphExecDestroy(p->iter_graph));
+    p->iter_graph = nullptr;
+  }
   return ABAC_OK;
 }
 

@@ -51,6 +51,11 @@ struct DevPlan {
   long long NS;        // nt * ms: scratch values per right-hand side
   double c0, cx, cy;   // (L s)_i = c0 s_i - cx (s_{i-1} + s_{i+1}) - cy (s_{i-nx} + s_{i+nx})
   double tau, tau2;
+  // variable coefficient a(x) of div(a grad u) (eq. (3.2)); both NULL for a = 1.
+  // coef_x: ny1 rows of Mx face weights (tau^2/2) a(x_{i+1/2}, y_j) / hx^2, i = 0..nx;
+  // coef_y (2D): My rows of nx face weights (tau^2/2) a(x_i, y_{j+1/2}) / hy^2, j = 0..ny.
+  const double* coef_x;
+  const double* coef_y;
   // spectral tables, stored in the transform precision
   const void* twx;     // 2*Mx complex twiddles exp(-2 pi i e/(2 Mx))
   const void* twy;     // 2*My complex twiddles (2D)

@@ -16,17 +16,39 @@ constexpr int kVecThreads = 256;
 constexpr int kVecPerThread = 16;
 constexpr int kVecMaxBlocks = 1024;
 
-// (L s)_i at spatial point (ix, iy) of one level, zero Dirichlet ghosts.
-__device__ __forceinline__ double apply_L(const DevPlan& P, const double* __restrict__ lvl, int i, int ix, int iy) {
-  const double c = lvl[i];
-  double sx = 0.0, sy = 0.0;
-  if (ix > 0) sx += lvl[i - 1];
-  if (ix < P.nx - 1) sx += lvl[i + 1];
+// Weights of L at one spatial point:
+//   (L s)_i = c s_i - w s_{i-1} - e s_{i+1} - so s_{i-nx} - no s_{i+nx}.
+// Constant coefficient: L = I - (tau^2/2) Delta_h (eq. (1.2)).  Variable coefficient:
+// L_a = I - (tau^2/2) Delta_{a,h} (eq. (3.2)) with the face weights of the plan; a
+// neighbour outside the grid is a zero Dirichlet value, so its weight stays in c.
+struct LCoef {
+  double c, w, e, so, no;
+};
+
+__device__ __forceinline__ LCoef l_coef(const DevPlan& P, int ix, int iy) {
+  if (!P.coef_x) return {P.c0, P.cx, P.cx, P.cy, P.cy};
+  const double* fx = P.coef_x + (size_t)iy * P.Mx + ix;
+  const double w = fx[0], e = fx[1];
+  double so = 0.0, no = 0.0;
   if (P.ny) {
-    if (iy > 0) sy += lvl[i - P.nx];
-    if (iy < P.ny - 1) sy += lvl[i + P.nx];
+    const double* fy = P.coef_y + (size_t)iy * P.nx + ix;
+    so = fy[0];
+    no = fy[P.nx];
   }
-  return P.c0 * c - P.cx * sx - P.cy * sy;
+  return {1.0 + (w + e) + (so + no), w, e, so, no};
+}
+
+// (L s)_i at spatial point (ix, iy) of one level.
+__device__ __forceinline__ double apply_L(const DevPlan& P, const LCoef& q, const double* __restrict__ lvl, int i,
+                                          int ix, int iy) {
+  double r = q.c * lvl[i];
+  if (ix > 0) r -= q.w * lvl[i - 1];
+  if (ix < P.nx - 1) r -= q.e * lvl[i + 1];
+  if (P.ny) {
+    if (iy > 0) r -= q.so * lvl[i - P.nx];
+    if (iy < P.ny - 1) r -= q.no * lvl[i + P.nx];
+  }
+  return r;
 }
 
 // One logical block of the matvec: spatial tile `tile`, forward levels [k0, k1) and
@@ -38,26 +60,27 @@ __device__ __forceinline__ double stencil_tile(const DevPlan& P, int mode, const
   const int i = tile * kStencilThreads + threadIdx.x;
   if (i >= m) return 0.0;
   const int ix = i % P.nx, iy = i / P.nx;
+  const LCoef q = l_coef(P, ix, iy);   // loaded once, reused on every level of the march
   const int k0 = chunk * P.st_chunk;
   const int k1 = min(k0 + P.st_chunk, n / 2);
   double acc = 0.0;
   // forward march state: x_{k-1}, x_{k-2} and L of them
   double zf1 = 0.0, zf2 = 0.0, Lf1 = 0.0, Lf2 = 0.0;
-  if (k0 >= 2) { zf2 = x[(size_t)(k0 - 2) * m + i]; Lf2 = apply_L(P, x + (size_t)(k0 - 2) * m, i, ix, iy); }
-  if (k0 >= 1) { zf1 = x[(size_t)(k0 - 1) * m + i]; Lf1 = apply_L(P, x + (size_t)(k0 - 1) * m, i, ix, iy); }
+  if (k0 >= 2) { zf2 = x[(size_t)(k0 - 2) * m + i]; Lf2 = apply_L(P, q, x + (size_t)(k0 - 2) * m, i, ix, iy); }
+  if (k0 >= 1) { zf1 = x[(size_t)(k0 - 1) * m + i]; Lf1 = apply_L(P, q, x + (size_t)(k0 - 1) * m, i, ix, iy); }
   // backward march state at kb = n-1-k0: x_kb, x_{kb-1} and L of them
   const int kb0 = n - 1 - k0;
-  double zb0 = x[(size_t)kb0 * m + i], Lb0 = apply_L(P, x + (size_t)kb0 * m, i, ix, iy);
-  double zb1 = x[(size_t)(kb0 - 1) * m + i], Lb1 = apply_L(P, x + (size_t)(kb0 - 1) * m, i, ix, iy);
+  double zb0 = x[(size_t)kb0 * m + i], Lb0 = apply_L(P, q, x + (size_t)kb0 * m, i, ix, iy);
+  double zb1 = x[(size_t)(kb0 - 1) * m + i], Lb1 = apply_L(P, q, x + (size_t)(kb0 - 1) * m, i, ix, iy);
   for (int k = k0; k < k1; ++k) {
     const double* lk = x + (size_t)k * m;
     const double zk = lk[i];
-    const double Lk = apply_L(P, lk, i, ix, iy);
+    const double Lk = apply_L(P, q, lk, i, ix, iy);
     const double out_f = Lk + Lf2 - 2.0 * zf1;          // (T x)_k
     const int kb = n - 1 - k;
     const double* lb2 = x + (size_t)(kb - 2) * m;
     const double zb2 = lb2[i];
-    const double Lb2 = apply_L(P, lb2, i, ix, iy);
+    const double Lb2 = apply_L(P, q, lb2, i, ix, iy);
     const double out_b = Lb0 + Lb2 - 2.0 * zb1;         // (T x)_kb
     if (mode >= STENCIL_RESIDUAL) {
       const double rf = f[(size_t)k * m + i] - out_f;
@@ -136,7 +159,8 @@ k_rhs(DevPlan P, const double* __restrict__ src, const double* __restrict__ psi0
     if (k == 0) {
       v = 0.5 * P.tau2 * s + P.tau * psi1[b * P.m + i] + psi0[b * P.m + i];
     } else if (k == 1) {
-      v -= apply_L(P, psi0 + b * P.m, i, i % P.nx, i / P.nx);
+      const int ix = i % P.nx, iy = i / P.nx;
+      v -= apply_L(P, l_coef(P, ix, iy), psi0 + b * P.m, i, ix, iy);
     }
     f[e] = v;
   }

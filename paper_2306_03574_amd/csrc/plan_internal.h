@@ -26,6 +26,10 @@ struct abac_plan {
   void* ws;
   size_t ws_bytes;
   bool own_ws;
+  // variable-coefficient face weights (workspace region) and the preconditioner's
+  // constant coefficient abar (1 for the constant-coefficient problem)
+  double* coef_ws;
+  double abar;
   // asynchronous solve bookkeeping
   MinresState* h_ring;   // host-mapped pinned memory, kSnapRing * B states written by the device
   hipEvent_t ring_ev[kSnapRing];
