@@ -46,9 +46,15 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 const int kTileCandidates[] = {64, 128, 256, 512, 1024};
 
-int default_wg(int L, int prec, int maxlds) {
+// a tile fits when its dynamic LDS plus a margin for the kernels' static LDS
+// (block reductions) fits the device's per-workgroup LDS
+bool tile_fits(int kind, int L, int wg, int prec, int maxlds) {
+  return transform_tile_valid(kind, L, wg, prec) && transform_lds_bytes(kind, L, wg, prec) + 8192 <= (size_t)maxlds;
+}
+
+int default_wg(int kind, int L, int prec, int maxlds) {
   for (int wg : {256, 512, 1024, 128, 64})
-    if (transform_tile_valid(L, wg, prec) && transform_lds_bytes(L, wg, prec) + 8192 <= (size_t)maxlds) return wg;
+    if (tile_fits(kind, L, wg, prec, maxlds)) return wg;
   return 0;
 }
 
@@ -98,8 +104,12 @@ abac_status describe(int nx, int ny, int nt, double T, double alpha, int prec, i
   }
   // matvec time chunk: the longest of 32/16/8 levels that still gives >= 2048 blocks
   // (a fixed rule per shape, since the chunk also fixes the grouping of <A z, z>)
+  // matvec blocks march over st_chunk levels (and their mirrors); longer marches
+  // re-read fewer warm-up levels, shorter ones give more blocks.  The rule depends on
+  // the shape only (not on the batch), so a batched solve sums its partials in the
+  // same order as a single one.
   P.st_chunk = 32;
-  while (P.st_chunk > 8 && (long long)stencil_blocks(P) * P.B < 2048) P.st_chunk /= 2;
+  while (P.st_chunk > 8 && stencil_blocks(P) < 512) P.st_chunk /= 2;
   P.maxparts = std::max(stencil_blocks(P), std::max(update_blocks(P), (P.nt * P.ny1 + 1) / 2));
   P.maxparts = (P.maxparts + 63) & ~63;
   P.prec = prec;
@@ -333,9 +343,12 @@ abac_status autotune(DevPlan& P, int prec, hipStream_t s, int maxlds) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     if (!g_tune_loaded) tune_file_load();
     auto it = g_tune.find(key);
-    if (it != g_tune.end()) {
+    // a cached choice is used only if every tile is still legal for these kernels
+    // (an entry written by another build of the library may not be)
+    if (it != g_tune.end() && tile_fits(TK_XFWD, 2 * P.Mx, it->second[0], prec, maxlds) &&
+        it->second[1] == P.wg_xi && (!P.ny || tile_fits(TK_Y, 2 * P.My, it->second[2], prec, maxlds)) &&
+        tile_fits(TK_TIME, P.nt, it->second[3], prec, maxlds)) {
       P.wg_x = it->second[0];
-      P.wg_xi = it->second[1];
       P.wg_y = it->second[2];
       P.wg_t = it->second[3];
       return ABAC_OK;
@@ -354,11 +367,11 @@ abac_status autotune(DevPlan& P, int prec, hipStream_t s, int maxlds) {
     HIP_TRY(hipMemcpyAsync(P.st, tmp.data(), sizeof(MinresState) * P.B, hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
   }
-  auto pick = [&](int L, int* field, auto launch) {
+  auto pick = [&](int kind, int L, int* field, auto launch) {
     int best = *field;
     float best_ms = 1e30f;
     for (int wg : kTileCandidates) {
-      if (!transform_tile_valid(L, wg, prec) || transform_lds_bytes(L, wg, prec) + 8192 > (size_t)maxlds) continue;
+      if (!tile_fits(kind, L, wg, prec, maxlds)) continue;
       *field = wg;
       const float ms = time_launches(s, launch);
       if (ms < best_ms) {
@@ -368,9 +381,9 @@ abac_status autotune(DevPlan& P, int prec, hipStream_t s, int maxlds) {
     }
     *field = best;
   };
-  pick(2 * P.Mx, &P.wg_x, [&] { return launch_dstx_fwd(P, prec, FWD_LANCZOS, 1, nullptr, s); });
-  if (P.ny) pick(2 * P.My, &P.wg_y, [&] { return launch_dsty(P, prec, 1, s); });
-  pick(P.nt, &P.wg_t, [&] { return launch_time(P, prec, 1, s); });
+  pick(TK_XFWD, 2 * P.Mx, &P.wg_x, [&] { return launch_dstx_fwd(P, prec, FWD_LANCZOS, 1, nullptr, s); });
+  if (P.ny) pick(TK_Y, 2 * P.My, &P.wg_y, [&] { return launch_dsty(P, prec, 1, s); });
+  pick(TK_TIME, P.nt, &P.wg_t, [&] { return launch_time(P, prec, 1, s); });
   // the last pass carries the <q, P^{-1} q> reduction: its tile stays at the fixed
   // default so the summation order (and the iterates) never depend on timing noise
   HIP_TRY(hipMemsetAsync(P.st, 0, sizeof(MinresState) * P.B, s));
@@ -499,15 +512,15 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
   int dev = 0, maxlds = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  P.wg_x = default_wg(2 * P.Mx, prec, maxlds);
+  P.wg_x = default_wg(TK_XFWD, 2 * P.Mx, prec, maxlds);
   // the last pass carries a reduction, so its tile follows a fixed rule (not timing):
   // the smallest legal tile, which keeps its LDS small and its occupancy high
   P.wg_xi = 0;
   for (int wg : kTileCandidates)
-    if (!P.wg_xi && transform_tile_valid(2 * P.Mx, wg, prec) && transform_lds_bytes(2 * P.Mx, wg, prec) + 8192 <= (size_t)maxlds)
+    if (!P.wg_xi && tile_fits(TK_XINV, 2 * P.Mx, wg, prec, maxlds))
       P.wg_xi = wg;
-  P.wg_y = ny ? default_wg(2 * P.My, prec, maxlds) : 256;
-  P.wg_t = default_wg(nt, prec, maxlds);
+  P.wg_y = ny ? default_wg(TK_Y, 2 * P.My, prec, maxlds) : 256;
+  P.wg_t = default_wg(TK_TIME, nt, prec, maxlds);
   if (prec != ABAC_PREC_NONE && (!P.wg_x || !P.wg_xi || !P.wg_y || !P.wg_t))
     return fail(ABAC_EINVAL, "transform does not fit the device LDS (" + std::to_string(maxlds) +
                                  " B); use the FP32 preconditioner for this size");

@@ -172,8 +172,11 @@ hipError_t launch_dstx_fwd(const DevPlan& P, int prec, int mode, int check, cons
 hipError_t launch_dsty(const DevPlan& P, int prec, int check, hipStream_t s);
 hipError_t launch_time(const DevPlan& P, int prec, int check, hipStream_t s);
 hipError_t launch_dstx_inv(const DevPlan& P, int prec, int mode, double* out, hipStream_t s);
-size_t transform_lds_bytes(int L, int wg, int prec);
-bool transform_tile_valid(int L, int wg, int prec);
+// transform kernel kinds (tile validity and LDS size differ per kind)
+enum TransformKind : int { TK_XFWD = 0, TK_XINV = 1, TK_Y = 2, TK_TIME = 3 };
+// dynamic LDS bytes of one workgroup (0 if the tile is not legal)
+size_t transform_lds_bytes(int kind, int L, int wg, int prec);
+bool transform_tile_valid(int kind, int L, int wg, int prec);
 int transform_tps(int L);
 
 }  // namespace abac

@@ -16,83 +16,125 @@ constexpr int kVecThreads = 256;
 constexpr int kVecPerThread = 16;
 constexpr int kVecMaxBlocks = 1024;
 
-// Weights of L at one spatial point:
+// Weights and neighbour offsets of L at one spatial point:
 //   (L s)_i = c s_i - w s_{i-1} - e s_{i+1} - so s_{i-nx} - no s_{i+nx}.
 // Constant coefficient: L = I - (tau^2/2) Delta_h (eq. (1.2)).  Variable coefficient:
-// L_a = I - (tau^2/2) Delta_{a,h} (eq. (3.2)) with the face weights of the plan; a
-// neighbour outside the grid is a zero Dirichlet value, so its weight stays in c.
+// L_a = I - (tau^2/2) Delta_{a,h} (eq. (3.2)) with the face weights of the plan.  A
+// neighbour outside the grid is a zero Dirichlet value: its face weight stays in c,
+// its own weight is 0 and its offset points back at the centre, so every load is
+// unconditional and in bounds (no divergent branches around the loads, which would
+// serialise them).
 struct LCoef {
   double c, w, e, so, no;
+  int ow, oe, os, on;   // offsets of the four neighbours (0 where outside the grid)
 };
 
 __device__ __forceinline__ LCoef l_coef(const DevPlan& P, int ix, int iy) {
-  if (!P.coef_x) return {P.c0, P.cx, P.cx, P.cy, P.cy};
-  const double* fx = P.coef_x + (size_t)iy * P.Mx + ix;
-  const double w = fx[0], e = fx[1];
-  double so = 0.0, no = 0.0;
-  if (P.ny) {
-    const double* fy = P.coef_y + (size_t)iy * P.nx + ix;
-    so = fy[0];
-    no = fy[P.nx];
+  double w = P.cx, e = P.cx, so = P.cy, no = P.cy;
+  if (P.coef_x) {
+    const double* fx = P.coef_x + (size_t)iy * P.Mx + ix;
+    w = fx[0];
+    e = fx[1];
+    so = no = 0.0;
+    if (P.ny) {
+      const double* fy = P.coef_y + (size_t)iy * P.nx + ix;
+      so = fy[0];
+      no = fy[P.nx];
+    }
   }
-  return {1.0 + (w + e) + (so + no), w, e, so, no};
+  LCoef q;
+  q.c = P.coef_x ? 1.0 + (w + e) + (so + no) : P.c0;
+  const bool hw = ix > 0, he = ix < P.nx - 1;
+  const bool hs = P.ny && iy > 0, hn = P.ny && iy < P.ny - 1;
+  q.w = hw ? w : 0.0;
+  q.e = he ? e : 0.0;
+  q.so = hs ? so : 0.0;
+  q.no = hn ? no : 0.0;
+  q.ow = hw ? -1 : 0;
+  q.oe = he ? 1 : 0;
+  q.os = hs ? -P.nx : 0;
+  q.on = hn ? P.nx : 0;
+  return q;
 }
 
-// (L s)_i at spatial point (ix, iy) of one level.
-__device__ __forceinline__ double apply_L(const DevPlan& P, const LCoef& q, const double* __restrict__ lvl, int i,
-                                          int ix, int iy) {
-  double r = q.c * lvl[i];
-  if (ix > 0) r -= q.w * lvl[i - 1];
-  if (ix < P.nx - 1) r -= q.e * lvl[i + 1];
-  if (P.ny) {
-    if (iy > 0) r -= q.so * lvl[i - P.nx];
-    if (iy < P.ny - 1) r -= q.no * lvl[i + P.nx];
-  }
-  return r;
+// The five values of one level that (L s)_i reads, and L applied to them.
+struct Lvl5 {
+  double c, w, e, s, n;
+};
+
+__device__ __forceinline__ Lvl5 load5(const LCoef& q, const double* __restrict__ lvl, int i) {
+  return {lvl[i], lvl[i + q.ow], lvl[i + q.oe], lvl[i + q.os], lvl[i + q.on]};
+}
+
+__device__ __forceinline__ double L_of(const LCoef& q, const Lvl5& v) {
+  return q.c * v.c - (q.w * v.w + q.e * v.e) - (q.so * v.s + q.no * v.n);
+}
+
+// (L s)_i of one level.
+__device__ __forceinline__ double apply_L(const LCoef& q, const double* __restrict__ lvl, int i) {
+  return L_of(q, load5(q, lvl, i));
 }
 
 // One logical block of the matvec: spatial tile `tile`, forward levels [k0, k1) and
-// their mirrors nt-1-k.  Returns this thread's contribution to the fused reduction.
-__device__ __forceinline__ double stencil_tile(const DevPlan& P, int mode, const double* __restrict__ x,
+// their mirrors nt-1-k.  Returns this thread's contribution to the fused reduction
+// (RES: sum of squared residuals against f; DOT: <Y T x, x>).  The march keeps L of
+// the two previous levels in registers; every load is unconditional, so the loads of
+// a step (and of the unrolled next step) are all in flight together.
+template <bool RES, bool DOT>
+__device__ __forceinline__ double stencil_tile(const DevPlan& P, const double* __restrict__ x,
                                                double* __restrict__ y, const double* __restrict__ f, int tile,
                                                int chunk) {
   const int n = P.nt, m = P.m;
   const int i = tile * kStencilThreads + threadIdx.x;
   if (i >= m) return 0.0;
-  const int ix = i % P.nx, iy = i / P.nx;
-  const LCoef q = l_coef(P, ix, iy);   // loaded once, reused on every level of the march
+  const LCoef q = l_coef(P, i % P.nx, i / P.nx);   // loaded once, reused on every level
   const int k0 = chunk * P.st_chunk;
   const int k1 = min(k0 + P.st_chunk, n / 2);
   double acc = 0.0;
-  // forward march state: x_{k-1}, x_{k-2} and L of them
-  double zf1 = 0.0, zf2 = 0.0, Lf1 = 0.0, Lf2 = 0.0;
-  if (k0 >= 2) { zf2 = x[(size_t)(k0 - 2) * m + i]; Lf2 = apply_L(P, q, x + (size_t)(k0 - 2) * m, i, ix, iy); }
-  if (k0 >= 1) { zf1 = x[(size_t)(k0 - 1) * m + i]; Lf1 = apply_L(P, q, x + (size_t)(k0 - 1) * m, i, ix, iy); }
+  // forward march state: x_{k-1} and L of x_{k-1}, x_{k-2} (zero before level 0); the
+  // loads come from a clamped level and are selected away, so they are unconditional
+  const int a2 = max(k0 - 2, 0), a1 = max(k0 - 1, 0);
+  const Lvl5 p2 = load5(q, x + (size_t)a2 * m, i), p1 = load5(q, x + (size_t)a1 * m, i);
+  double Lf2 = k0 >= 2 ? L_of(q, p2) : 0.0;
+  double zf1 = k0 >= 1 ? p1.c : 0.0, Lf1 = k0 >= 1 ? L_of(q, p1) : 0.0;
   // backward march state at kb = n-1-k0: x_kb, x_{kb-1} and L of them
   const int kb0 = n - 1 - k0;
-  double zb0 = x[(size_t)kb0 * m + i], Lb0 = apply_L(P, q, x + (size_t)kb0 * m, i, ix, iy);
-  double zb1 = x[(size_t)(kb0 - 1) * m + i], Lb1 = apply_L(P, q, x + (size_t)(kb0 - 1) * m, i, ix, iy);
+  double zb0 = x[(size_t)kb0 * m + i], Lb0 = apply_L(q, x + (size_t)kb0 * m, i);
+  double zb1 = x[(size_t)(kb0 - 1) * m + i], Lb1 = apply_L(q, x + (size_t)(kb0 - 1) * m, i);
+  // two levels per trip (chunks are even): both steps' loads are issued together
+#pragma unroll 2
   for (int k = k0; k < k1; ++k) {
-    const double* lk = x + (size_t)k * m;
-    const double zk = lk[i];
-    const double Lk = apply_L(P, q, lk, i, ix, iy);
+    const Lvl5 cf = load5(q, x + (size_t)k * m, i);              // forward level k
+    const Lvl5 cb = load5(q, x + (size_t)(n - 3 - k) * m, i);    // backward level kb - 2
+    const double zk = cf.c, Lk = L_of(q, cf);
     const double out_f = Lk + Lf2 - 2.0 * zf1;          // (T x)_k
-    const int kb = n - 1 - k;
-    const double* lb2 = x + (size_t)(kb - 2) * m;
-    const double zb2 = lb2[i];
-    const double Lb2 = apply_L(P, q, lb2, i, ix, iy);
-    const double out_b = Lb0 + Lb2 - 2.0 * zb1;         // (T x)_kb
-    if (mode >= STENCIL_RESIDUAL) {
+    const double zb2 = cb.c, Lb2 = L_of(q, cb);
+    const double out_b = Lb0 + Lb2 - 2.0 * zb1;         // (T x)_kb, kb = n-1-k
+    if (RES) {
       const double rf = f[(size_t)k * m + i] - out_f;
-      const double rb = f[(size_t)kb * m + i] - out_b;
+      const double rb = f[(size_t)(n - 1 - k) * m + i] - out_b;
       acc += rf * rf + rb * rb;
     } else {
       y[(size_t)(n - 1 - k) * m + i] = out_f;           // Y reverses time
-      y[(size_t)(n - 1 - kb) * m + i] = out_b;
-      if (mode == STENCIL_MINRES) acc += out_f * zb0 + out_b * zk;
+      y[(size_t)k * m + i] = out_b;
+      if (DOT) acc += out_f * zb0 + out_b * zk;
     }
-    zf2 = zf1; Lf2 = Lf1; zf1 = zk; Lf1 = Lk;
+    Lf2 = Lf1; zf1 = zk; Lf1 = Lk;
     zb0 = zb1; Lb0 = Lb1; zb1 = zb2; Lb1 = Lb2;
+  }
+  return acc;
+}
+
+// The blocks of one right-hand side (grid-stride, XCD-aware order).
+template <bool RES, bool DOT>
+__device__ __forceinline__ double stencil_run(const DevPlan& P, const double* __restrict__ x, double* __restrict__ y,
+                                              const double* __restrict__ f) {
+  const int tiles = (P.m + kStencilThreads - 1) / kStencilThreads;
+  const int nblk = stencil_blocks(P);
+  double acc = 0.0;
+  for (int w = blockIdx.x; w < nblk; w += gridDim.x) {
+    const int lb = xcd_remap(w, nblk);
+    acc += stencil_tile<RES, DOT>(P, x, y, f, lb % tiles, lb / tiles);
   }
   return acc;
 }
@@ -132,14 +174,15 @@ k_stencil(DevPlan P, int mode, const double* __restrict__ xin, double* __restric
   x += (size_t)b * P.N;
   if (y) y += (size_t)b * P.N;
   const double* f = fref ? fref + (size_t)b * P.N : nullptr;
-  const int tiles = (P.m + kStencilThreads - 1) / kStencilThreads;
-  const int nblk = stencil_blocks(P);
-  double acc = 0.0;
-  for (int w = blockIdx.x; w < nblk; w += gridDim.x) {
-    const int lb = xcd_remap(w, nblk);
-    acc += stencil_tile(P, mode, x, y, f, lb % tiles, lb / tiles);
+  double acc;
+  if (mode == STENCIL_PLAIN) {
+    stencil_run<false, false>(P, x, y, f);
+    return;
+  } else if (mode == STENCIL_MINRES) {
+    acc = stencil_run<false, true>(P, x, y, f);
+  } else {
+    acc = stencil_run<true, false>(P, x, y, f);
   }
-  if (mode == STENCIL_PLAIN) return;
   const double bs = block_sum(acc);
   if (threadIdx.x == 0) part_slot(P, part_kind, b)[blockIdx.x] = bs;
 }
@@ -159,8 +202,7 @@ k_rhs(DevPlan P, const double* __restrict__ src, const double* __restrict__ psi0
     if (k == 0) {
       v = 0.5 * P.tau2 * s + P.tau * psi1[b * P.m + i] + psi0[b * P.m + i];
     } else if (k == 1) {
-      const int ix = i % P.nx, iy = i / P.nx;
-      v -= apply_L(P, l_coef(P, ix, iy), psi0 + b * P.m, i, ix, iy);
+      v -= apply_L(l_coef(P, i % P.nx, i / P.nx), psi0 + b * P.m, i);
     }
     f[e] = v;
   }

@@ -26,10 +26,36 @@ namespace abac {
 namespace {
 
 template <int L, int WG> constexpr int seqs_of() { return WG / fft_tps<L>(); }
-template <typename T, int L, int WG>
+
+// LDS bytes of one workgroup: the interleaved sequences; the inverse x pass reuses
+// the region for its FP64 output staging; the y pass (length <= 1024) also holds its
+// twiddle table, and the time pass its twiddles, spectral coefficients (A_k, B_k) and
+// a^{+-t} scalings, each read once per block instead of once per butterfly or element.
+template <typename T, int L, int WG, int KIND>
+constexpr size_t lds_of() {
+  constexpr size_t c = sizeof(cplx<T>);
+  constexpr size_t data = (size_t)seqs_of<L, WG>() * L * c;
+  if constexpr (KIND == TK_XINV) {
+    constexpr size_t ostage = (size_t)2 * seqs_of<L, WG>() * (L / 2 + 1) * sizeof(double);
+    return data > ostage ? data : ostage;
+  } else if constexpr (KIND == TK_Y) {
+    return data + (size_t)L * c;
+  } else if constexpr (KIND == TK_TIME) {
+    return data + (size_t)3 * L * c + (size_t)2 * L * sizeof(T);
+  } else {
+    return data;
+  }
+}
+
+template <typename T, int L, int WG, int KIND>
 constexpr bool tile_ok() {
-  return WG >= fft_tps<L>() && WG % fft_tps<L>() == 0 && WG % 64 == 0 &&
-         (size_t)seqs_of<L, WG>() * L * sizeof(cplx<T>) <= kMaxTransformLds;
+  return WG >= fft_tps<L>() && WG % fft_tps<L>() == 0 && WG % 64 == 0 && lds_of<T, L, WG, KIND>() <= kMaxTransformLds;
+}
+
+// Copy an n-entry table into LDS (the caller places the barrier).
+template <typename V>
+__device__ __forceinline__ void stage_table(V* dst, const V* __restrict__ src, int n) {
+  for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
 }
 
 template <typename T>
@@ -73,6 +99,20 @@ __device__ __forceinline__ void tile_out(TD* __restrict__ dst, const TS* src, in
   }
 }
 
+// Copy cnt <= PER * WG contiguous values of src into LDS (converted to TD): every
+// load of a thread is issued (from a clamped, in-bounds index) before any is used.
+template <int PER, int WG, typename TS, typename TD>
+__device__ __forceinline__ void stage_in(TD* dst, const TS* __restrict__ src, int cnt) {
+  TS v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) v[u] = src[min((int)threadIdx.x + u * WG, cnt - 1)];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * WG;
+    if (e < cnt) dst[e] = (TD)v[u];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // first pass: DST-I along x of every row (FP64 in, transform precision out),
 // optionally fused with the Lanczos step q = sig_j A Z_j - delta v_j - gamma_j v_{j-1}
@@ -112,14 +152,32 @@ k_dstx_fwd(DevPlan P, int mode, int check, const double* __restrict__ in) {
   const int nrows = min(2 * S, rows - row0);
   const size_t base = (size_t)row0 * nx;
   const int cnt = nrows * nx;
+  // cnt <= 2 S nx < WG * R: each thread stages at most R values, in batches whose
+  // loads (clamped to the tile, so unconditional) are all issued before they are used
+  constexpr int BATCH = 4;
   if (mode == FWD_LANCZOS) {
-    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-      const double q = cA * src[base + e] - cB * vj[base + e] - cC * vjm1[base + e];
-      qout[base + e] = q;
-      stage[e] = (T)q;
+#pragma unroll
+    for (int u0 = 0; u0 < R; u0 += BATCH) {
+      double a[BATCH], bv[BATCH], cv[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const size_t e = base + min((int)threadIdx.x + (u0 + u) * WG, cnt - 1);
+        a[u] = src[e];
+        bv[u] = vj[e];
+        cv[u] = vjm1[e];
+      }
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int e = threadIdx.x + (u0 + u) * WG;
+        if (e < cnt) {
+          const double q = cA * a[u] - cB * bv[u] - cC * cv[u];
+          qout[base + e] = q;
+          stage[e] = (T)q;
+        }
+      }
     }
   } else {
-    for (int e = threadIdx.x; e < cnt; e += blockDim.x) stage[e] = (T)src[base + e];
+    stage_in<R, WG>(stage, src + base, cnt);
   }
   __syncthreads();
   const int s = threadIdx.x % S, j = threadIdx.x / S;
@@ -173,7 +231,8 @@ k_dsty(DevPlan P, int check) {
   using C = cplx<T>;
   constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_of<L, WG>(), My = L / 2;
   extern __shared__ __align__(16) unsigned char smem[];
-  C* lds = reinterpret_cast<C*>(smem);
+  C* tws = reinterpret_cast<C*>(smem);
+  C* lds = tws + L;
   const int b = blockIdx.y;
   if (check && P.st[b].state != ST_RUNNING) return;
   const int cpairs = P.Mx / 2;
@@ -199,7 +258,9 @@ k_dsty(DevPlan P, int check) {
     }
     v[i] = z;
   }
-  fft_seq<T, L, false>(v, j, lds + s, S, reinterpret_cast<const C*>(P.twy));
+  stage_table(tws, reinterpret_cast<const C*>(P.twy), L);
+  __syncthreads();
+  fft_seq<T, L, false>(v, j, lds + s, S, tws);
   const T scl = (T)(1.0 / sqrt((double)L));
   if (!valid) return;
 #pragma unroll
@@ -222,8 +283,7 @@ k_dsty(DevPlan P, int check) {
 // (k, nt-k) with a single evaluation of Ma_k, Mb_k.  Input and output in LDS, natural
 // order; `scale` folds in the 1/nt of the inverse DFT.
 template <typename T, int NT>
-__device__ __forceinline__ void spectral_pairs(cplx<T>* my, int S, int j, const cplx<T>* __restrict__ abk, T ba, T bb,
-                                               T scale) {
+__device__ __forceinline__ void spectral_pairs(cplx<T>* my, int S, int j, const cplx<T>* abk, T ba, T bb, T scale) {
   using C = cplx<T>;
   constexpr int R = FftShape<NT>::R, TPS = NT / R;
   constexpr int NU = R / 2 + 1;
@@ -248,7 +308,12 @@ k_time(DevPlan P, int check) {
   using C = cplx<T>;
   constexpr int R = FftShape<NT>::R, TPS = NT / R, S = seqs_of<NT, WG>();
   extern __shared__ __align__(16) unsigned char smem[];
-  C* lds = reinterpret_cast<C*>(smem);
+  // LDS: twiddles [NT], (A_k, B_k) [2 NT], a^t [NT], a^-t [NT], then the sequences
+  C* tws = reinterpret_cast<C*>(smem);
+  C* abk = tws + NT;
+  T* sc = reinterpret_cast<T*>(abk + 2 * NT);
+  T* sci = sc + NT;
+  C* lds = reinterpret_cast<C*>(sci + NT);
   const int b = blockIdx.y;
   if (check && P.st[b].state != ST_RUNNING) return;
   const int s = threadIdx.x % S, j = threadIdx.x / S;
@@ -257,22 +322,25 @@ k_time(DevPlan P, int check) {
   const bool valid = pair < npairs;
   const int ld = npairs;
   C* g = reinterpret_cast<C*>(reinterpret_cast<T*>(P.scratch) + (size_t)b * P.NS) + pair;
-  const T* __restrict__ sc = reinterpret_cast<const T*>(P.sc);
-  const T* __restrict__ sci = reinterpret_cast<const T*>(P.sci);
-  const C* __restrict__ abk = reinterpret_cast<const C*>(P.abk);
-  const C* __restrict__ tw = reinterpret_cast<const C*>(P.twt);
   const T* __restrict__ beta = reinterpret_cast<const T*>(P.beta);
   const T ba = valid ? beta[2 * pair] : (T)1;
   const T bb = valid ? beta[2 * pair + 1] : (T)1;
   C* my = lds + s;
   C v[R];
-  // Y then D: e_t = a^t g_{nt-1-t}
+  // Y: e_t = g_{nt-1-t} (the D scaling follows once the table is in LDS)
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const int t = j + i * TPS;
-    const C z = valid ? g[(size_t)(NT - 1 - t) * ld] : C{0, 0};
-    v[i] = cscale(z, sc[t]);
+    v[i] = valid ? g[(size_t)(NT - 1 - t) * ld] : C{0, 0};
   }
+  stage_table(tws, reinterpret_cast<const C*>(P.twt), NT);
+  stage_table(abk, reinterpret_cast<const C*>(P.abk), 2 * NT);
+  stage_table(sc, reinterpret_cast<const T*>(P.sc), NT);
+  stage_table(sci, reinterpret_cast<const T*>(P.sci), NT);
+  __syncthreads();
+  const C* tw = tws;
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = cscale(v[i], sc[j + i * TPS]);
   const T half_inv_n = (T)(0.5 / NT);
 #pragma unroll 1
   for (int rep = 0; rep < 2; ++rep) {
@@ -340,8 +408,8 @@ k_dstx_inv(DevPlan P, int mode, double* __restrict__ outp) {
   const int row0 = blockIdx.x * 2 * S;
   const int nrows = min(2 * S, rows - row0);
   const T* scr = reinterpret_cast<const T*>(P.scratch) + (size_t)b * P.NS + (size_t)row0 * Mx;
-  const int cnt = nrows * Mx;
-  for (int e = threadIdx.x; e < cnt; e += blockDim.x) stage[e] = scr[e];
+  const int cnt = nrows * Mx;   // <= 2 S Mx = WG * R
+  stage_in<R, WG>(stage, scr, cnt);
   __syncthreads();
   const int s = threadIdx.x % S, j = threadIdx.x / S;
   const int ra = 2 * s, rb = 2 * s + 1;
@@ -377,22 +445,34 @@ k_dstx_inv(DevPlan P, int mode, double* __restrict__ outp) {
   }
   __syncthreads();
   double* o = out + (size_t)row0 * nx;
-  const int total = nrows * nx;
+  const int total = nrows * nx;   // < WG * R
   double acc = 0.0;
   {
     const double* qq = q ? q + (size_t)row0 * nx : nullptr;
-    int e = threadIdx.x;
-    int r = e / nx, c = e - r * nx;
-    const int dr = blockDim.x / nx, dc = blockDim.x - dr * nx;
-    for (; e < total; e += blockDim.x) {
-      const double val = ostage[r * ldo + c];
-      o[e] = val;
-      if (qq) acc += val * qq[e];
-      r += dr;
-      c += dc;
-      if (c >= nx) {
-        c -= nx;
-        ++r;
+    int r = (int)threadIdx.x / nx, c = (int)threadIdx.x - r * nx;
+    const int dr = WG / nx, dc = WG - dr * nx;
+    constexpr int BATCH = 8;
+#pragma unroll
+    for (int u0 = 0; u0 < R; u0 += BATCH) {
+      double qv[BATCH];
+      if (qq) {
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) qv[u] = qq[min((int)threadIdx.x + (u0 + u) * WG, total - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int e = threadIdx.x + (u0 + u) * WG;
+        if (e < total) {
+          const double val = ostage[r * ldo + c];
+          o[e] = val;
+          if (qq) acc += val * qv[u];
+        }
+        r += dr;
+        c += dc;
+        if (c >= nx) {
+          c -= nx;
+          ++r;
+        }
       }
     }
   }
@@ -406,13 +486,13 @@ k_dstx_inv(DevPlan P, int mode, double* __restrict__ outp) {
 // ---------------------------------------------------------------------------
 template <typename T, int L, int WG>
 hipError_t launch_x_fwd_t(const DevPlan& P, int mode, int check, const double* in, hipStream_t s) {
-  if constexpr (!tile_ok<T, L, WG>()) {
+  if constexpr (!tile_ok<T, L, WG, TK_XFWD>()) {
     return hipErrorInvalidValue;
   } else {
     constexpr int S = seqs_of<L, WG>();
     const int rows = P.nt * P.ny1;
     dim3 grid((rows + 2 * S - 1) / (2 * S), P.B);
-    const size_t lds = (size_t)S * L * sizeof(cplx<T>);
+    const size_t lds = lds_of<T, L, WG, TK_XFWD>();
     hipLaunchKernelGGL((k_dstx_fwd<T, L, WG>), grid, dim3(WG), lds, s, P, mode, check, in);
     return hipGetLastError();
   }
@@ -420,13 +500,13 @@ hipError_t launch_x_fwd_t(const DevPlan& P, int mode, int check, const double* i
 
 template <typename T, int L, int WG>
 hipError_t launch_x_inv_t(const DevPlan& P, int mode, double* out, hipStream_t s) {
-  if constexpr (!tile_ok<T, L, WG>()) {
+  if constexpr (!tile_ok<T, L, WG, TK_XINV>()) {
     return hipErrorInvalidValue;
   } else {
     constexpr int S = seqs_of<L, WG>();
     const int rows = P.nt * P.ny1;
     dim3 grid((rows + 2 * S - 1) / (2 * S), P.B);
-    const size_t lds = std::max((size_t)S * L * sizeof(cplx<T>), (size_t)2 * S * (L / 2 + 1) * sizeof(double));
+    const size_t lds = lds_of<T, L, WG, TK_XINV>();
     hipLaunchKernelGGL((k_dstx_inv<T, L, WG>), grid, dim3(WG), lds, s, P, mode, out);
     return hipGetLastError();
   }
@@ -434,14 +514,14 @@ hipError_t launch_x_inv_t(const DevPlan& P, int mode, double* out, hipStream_t s
 
 template <typename T, int L, int WG>
 hipError_t launch_y_t(const DevPlan& P, int check, hipStream_t s) {
-  if constexpr (!tile_ok<T, L, WG>()) {
+  if constexpr (!tile_ok<T, L, WG, TK_Y>()) {
     return hipErrorInvalidValue;
   } else {
     constexpr int S = seqs_of<L, WG>();
     const int cpairs = P.Mx / 2;
     const int bpl = (cpairs + S - 1) / S;
     dim3 grid(bpl * P.nt, P.B);
-    const size_t lds = (size_t)S * L * sizeof(cplx<T>);
+    const size_t lds = lds_of<T, L, WG, TK_Y>();
     hipLaunchKernelGGL((k_dsty<T, L, WG>), grid, dim3(WG), lds, s, P, check);
     return hipGetLastError();
   }
@@ -449,13 +529,13 @@ hipError_t launch_y_t(const DevPlan& P, int check, hipStream_t s) {
 
 template <typename T, int NT, int WG>
 hipError_t launch_time_t(const DevPlan& P, int check, hipStream_t s) {
-  if constexpr (!tile_ok<T, NT, WG>()) {
+  if constexpr (!tile_ok<T, NT, WG, TK_TIME>()) {
     return hipErrorInvalidValue;
   } else {
     constexpr int S = seqs_of<NT, WG>();
     const int npairs = P.ms / 2;
     dim3 grid((npairs + S - 1) / S, P.B);
-    const size_t lds = (size_t)S * NT * sizeof(cplx<T>);
+    const size_t lds = lds_of<T, NT, WG, TK_TIME>();
     hipLaunchKernelGGL((k_time<T, NT, WG>), grid, dim3(WG), lds, s, P, check);
     return hipGetLastError();
   }
@@ -515,10 +595,36 @@ hipError_t time_dispatch(const DevPlan& P, int check, hipStream_t s) {
 #undef CALL
 }
 
-template <typename T> hipError_t tile_check_t(int L, int wg) {
-#define CALL(LL, WW) (tile_ok<T, LL, WW>() ? hipSuccess : hipErrorInvalidValue)
+template <typename T, int KIND> hipError_t tile_check_t(int L, int wg) {
+#define CALL(LL, WW) (tile_ok<T, LL, WW, KIND>() ? hipSuccess : hipErrorInvalidValue)
   ABAC_SWITCH_L(L, wg, CALL)
 #undef CALL
+}
+
+template <typename T, int KIND> size_t lds_bytes_t(int L, int wg) {
+#define CALL(LL, WW) lds_of<T, LL, WW, KIND>()
+  ABAC_SWITCH_L(L, wg, CALL)
+#undef CALL
+}
+
+template <typename T> hipError_t tile_check_k(int kind, int L, int wg) {
+  switch (kind) {
+    case TK_XFWD: return tile_check_t<T, TK_XFWD>(L, wg);
+    case TK_XINV: return tile_check_t<T, TK_XINV>(L, wg);
+    case TK_Y: return tile_check_t<T, TK_Y>(L, wg);
+    case TK_TIME: return tile_check_t<T, TK_TIME>(L, wg);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T> size_t lds_bytes_k(int kind, int L, int wg) {
+  switch (kind) {
+    case TK_XFWD: return lds_bytes_t<T, TK_XFWD>(L, wg);
+    case TK_XINV: return lds_bytes_t<T, TK_XINV>(L, wg);
+    case TK_Y: return lds_bytes_t<T, TK_Y>(L, wg);
+    case TK_TIME: return lds_bytes_t<T, TK_TIME>(L, wg);
+    default: return 0;
+  }
 }
 
 }  // namespace
@@ -539,8 +645,8 @@ hipError_t launch_dstx_inv(const DevPlan& P, int prec, int mode, double* out, hi
   return prec ? x_inv_dispatch<float>(P, mode, out, s) : x_inv_dispatch<double>(P, mode, out, s);
 }
 
-bool transform_tile_valid(int L, int wg, int prec) {
-  return (prec ? tile_check_t<float>(L, wg) : tile_check_t<double>(L, wg)) == hipSuccess;
+bool transform_tile_valid(int kind, int L, int wg, int prec) {
+  return (prec ? tile_check_k<float>(kind, L, wg) : tile_check_k<double>(kind, L, wg)) == hipSuccess;
 }
 
 int transform_tps(int L) {
@@ -566,9 +672,9 @@ int dstx_blocks(const DevPlan& P, int wg) {
   return (rows + 2 * S - 1) / (2 * S);
 }
 
-size_t transform_lds_bytes(int L, int wg, int prec) {
-  const size_t c = prec ? sizeof(float2) : sizeof(double2);
-  return (size_t)(wg / transform_tps(L)) * L * c;
+size_t transform_lds_bytes(int kind, int L, int wg, int prec) {
+  if (!transform_tile_valid(kind, L, wg, prec)) return 0;
+  return prec ? lds_bytes_k<float>(kind, L, wg) : lds_bytes_k<double>(kind, L, wg);
 }
 
 }  // namespace abac
