@@ -33,7 +33,7 @@ WORKLOADS = {
     "wave1d_63x64": dict(nx=63, ny=0, nt=64, alpha=1e-3, batch=1, source="manufactured1d"),
     "serving_mix": dict(nx=0, ny=0, nt=0, alpha=0.0, batch=1, source="serving"),
 }
-KERNEL_CLASSES = ["stencil", "dstx_fwd", "dsty", "time", "dstx_inv", "update", "residual", "init", "rhs", "fin"]
+KERNEL_CLASSES = ["stencil", "dstx_fwd", "dsty", "time", "dstx_inv", "update", "form", "residual", "init", "rhs", "fin"]
 
 
 def log(msg):
@@ -73,8 +73,12 @@ def algorithmic_bytes(w, prec, iters_total, solves):
       dsty      2 s NS         (read + write scratch) per launch, 2 launches per apply
       time      2 s NS         (read + write scratch) per apply
       dstx_inv  s NS + 16 N    (read scratch, write p, read q) per apply
-      update    72 N           (read z, w1, w2, x, r, v; write w, x, r) per iteration
-      init      56 N           (read f; write r, v1, v0, w0, w1, u) per solve
+      update    24 N           (read r, v; write r) per iteration while the Krylov basis
+                               is resident (iterations 1..12), 72 N after it (also
+                               read z, w1, w2, x; write w, x)
+      form      8 (k+1) N      (read z_1..z_k, write u) once per solve of k <= 12
+                               iterations (the convergence check)
+      init      40 N           (read f; write r, v1, v0, u) per solve
     """
     nx, ny, nt = w["nx"], w["ny"], w["nt"]
     N = nt * nx * max(ny, 1)
@@ -87,8 +91,9 @@ def algorithmic_bytes(w, prec, iters_total, solves):
         "dsty": 2 * (2 * s * NS) * applies if ny else 0,
         "time": 2 * s * NS * applies,
         "dstx_inv": (s * NS + 16 * N) * applies,
-        "update": 72 * N * iters_total,
-        "init": 56 * N * solves,
+        "update": 24 * N * iters_total,
+        "form": 8 * N * (iters_total + solves),
+        "init": 40 * N * solves,
     }
 
 

@@ -153,12 +153,13 @@ enum {
   ABAC_K_DSTY = 2,      /* y-direction DST pass (2D, both directions)   */
   ABAC_K_TIME = 3,      /* per-mode time pipeline K Y K Y               */
   ABAC_K_DSTX_INV = 4,  /* last spatial DST pass (x)                    */
-  ABAC_K_UPDATE = 5,    /* MINRES w / x / r update and ||r||^2          */
+  ABAC_K_UPDATE = 5,    /* MINRES residual (and late w / x) update      */
   ABAC_K_RESIDUAL = 6,  /* explicit residual check                      */
   ABAC_K_INIT = 7,      /* solve set-up                                 */
   ABAC_K_RHS = 8,       /* right-hand side assembly                     */
   ABAC_K_FIN = 9,       /* per-RHS scalar steps (sums of partials)      */
-  ABAC_K_COUNT = 10
+  ABAC_K_FORM = 10,     /* stopping test; iterate from the resident basis */
+  ABAC_K_COUNT = 11
 };
 abac_status abac_profile_enable(abac_plan *plan, int on);
 abac_status abac_profile_read(abac_plan *plan, int kernel, double *total_ms, long long *launches);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libabac.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, EBUDGET, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7
 PREC = {"fp64": 0, "fp32": 1, "none": 2}
 KERNELS = {"stencil": 0, "dstx_fwd": 1, "dsty": 2, "time": 3, "dstx_inv": 4, "update": 5,
-           "residual": 6, "init": 7, "rhs": 8, "fin": 9}
+           "residual": 6, "init": 7, "rhs": 8, "fin": 9, "form": 10}
 
 EXPORTED = [
     "abac_workspace_bytes", "abac_plan_create", "abac_plan_destroy", "abac_build_rhs", "abac_apply_A",

@@ -59,7 +59,9 @@ int default_wg(int kind, int L, int prec, int maxlds) {
 }
 
 struct Layout {
-  size_t twx, twy, twt, beta, abk, sc, sci, coef, scratch, vec[8], st, partials, counters, total;
+  // vectors: V x3, Z x kZSlots, W x2, R
+  static constexpr int kVecs = 3 + kZSlots + 2 + 1;
+  size_t twx, twy, twt, beta, abk, sc, sci, coef, scratch, vec[kVecs], kcoef, st, partials, counters, total;
 };
 
 // Validate the problem and fill the size fields of a DevPlan.
@@ -131,7 +133,8 @@ Layout make_layout(const DevPlan& P, int prec) {
   Lo.sci = take(real * P.nt);
   Lo.coef = take(sizeof(double) * ((size_t)P.ny1 * P.Mx + (P.ny ? (size_t)P.My * P.nx : 0)));
   Lo.scratch = take(prec == ABAC_PREC_NONE ? 0 : real * (size_t)P.NS * P.B);
-  for (int i = 0; i < 8; ++i) Lo.vec[i] = take(sizeof(double) * (size_t)P.N * P.B);
+  for (int i = 0; i < Layout::kVecs; ++i) Lo.vec[i] = take(sizeof(double) * (size_t)P.N * P.B);
+  Lo.kcoef = take(sizeof(double) * 3 * kBasis * P.B);
   Lo.st = take(sizeof(MinresState) * P.B);
   Lo.partials = take(sizeof(double) * (size_t)P.maxparts * P.B * PART_KINDS);
   Lo.counters = take(sizeof(unsigned) * P.B);
@@ -219,6 +222,8 @@ abac_status enqueue_iteration(abac_plan* p) {
   abac_status s = enqueue_pinv(p, nullptr, nullptr, 2);
   if (s != ABAC_OK) return s;
   RUN(ABAC_K_UPDATE, launch_update(P, p->u, p->stream));
+  RUN(ABAC_K_FIN, launch_fin(P, FIN_RNORM, 0.0, 0, p->stream));
+  RUN(ABAC_K_FORM, launch_form(P, p->u, p->stream));
   RUN(ABAC_K_RESIDUAL, launch_stencil(P, STENCIL_RESIDUAL, p->u, nullptr, p->f, p->stream));
   RUN(ABAC_K_FIN, launch_fin(P, FIN_RES, 0.0, 0, p->stream));
   return ABAC_OK;
@@ -546,9 +551,10 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
   P.sci = base + Lo.sci;
   P.scratch = base + Lo.scratch;
   for (int i = 0; i < 3; ++i) P.V[i] = reinterpret_cast<double*>(base + Lo.vec[i]);
-  for (int i = 0; i < 2; ++i) P.Z[i] = reinterpret_cast<double*>(base + Lo.vec[3 + i]);
-  for (int i = 0; i < 2; ++i) P.W[i] = reinterpret_cast<double*>(base + Lo.vec[5 + i]);
-  P.R = reinterpret_cast<double*>(base + Lo.vec[7]);
+  for (int i = 0; i < kZSlots; ++i) P.Z[i] = reinterpret_cast<double*>(base + Lo.vec[3 + i]);
+  for (int i = 0; i < 2; ++i) P.W[i] = reinterpret_cast<double*>(base + Lo.vec[3 + kZSlots + i]);
+  P.R = reinterpret_cast<double*>(base + Lo.vec[3 + kZSlots + 2]);
+  P.kcoef = reinterpret_cast<double*>(base + Lo.kcoef);
   P.st = reinterpret_cast<MinresState*>(base + Lo.st);
   P.partials = reinterpret_cast<double*>(base + Lo.partials);
   P.counters = reinterpret_cast<unsigned*>(base + Lo.counters);
@@ -781,6 +787,8 @@ abac_status abac_minres_finish(abac_plan* p, int* iters, double* relres, int* st
         (h[b].status == ABAC_OK && h[b].iter > 0 && h[b].res2 > h[b].tol2 * h[b].bnorm2))
       report = true;
   if (report) {
+    RUN(ABAC_K_FIN, launch_fin(p->P, FIN_FINAL, 0.0, 0, p->stream));
+    RUN(ABAC_K_FORM, launch_form(p->P, p->u, p->stream));
     RUN(ABAC_K_RESIDUAL, launch_stencil(p->P, STENCIL_REPORT, p->u, nullptr, p->f, p->stream));
     RUN(ABAC_K_FIN, launch_fin(p->P, FIN_REPORT, 0.0, 0, p->stream));
     HIP_TRY(hipMemcpyAsync(h.data(), p->P.st, sizeof(MinresState) * p->P.B, hipMemcpyDeviceToHost, p->stream));

@@ -14,6 +14,16 @@ enum : int { ST_IDLE = 0, ST_RUNNING = 1, ST_DONE = 2 };
 constexpr int kSnapRing = 16;   // host snapshot slots per right-hand side
 constexpr size_t kMaxTransformLds = 128 * 1024;   // dynamic LDS per transform block
 
+// Resident Krylov basis: z_1 .. z_kBasis each keep a slot of their own, and the
+// iterate is formed from them (x_j = sum_l y_l z_l) only when a residual check, a
+// breakdown or the end of the solve needs it, so an iteration updates just the
+// residual vector.  From z_{kBasis+1} on, z alternates between two more slots and
+// w and x follow the classic three-term recurrences (after one flush that forms x,
+// w_kBasis and w_{kBasis-1} from the basis).
+constexpr int kBasis = 12;
+constexpr int kZSlots = kBasis + 2;
+__host__ __device__ inline int zslot(int j) { return j <= kBasis ? j - 1 : kBasis + (j & 1); }
+
 struct MinresState {
   double gamma;     // gamma_j, current Lanczos off-diagonal
   double sig;       // 1/gamma_j: scale of the stored (unnormalised) v_j and z_j
@@ -34,9 +44,13 @@ struct MinresState {
   int state;        // ST_*
   int status;       // abac_status of this right-hand side
   int explicit_mode;
-  int need_check;   // set by the residual kernel: confirm convergence explicitly
+  int need_check;   // set by the form kernel: confirm convergence explicitly
   int lucky;        // gamma_{j+1} == 0: the Krylov space is invariant
   int snap;         // sequence number of the next host snapshot
+  int nbasis;       // basis slots with coefficients (basis phase)
+  int basis_dirty;  // u does not yet hold the iterate of the basis coefficients
+  int form_now;     // this iteration forms u from the basis (flush: also w_j, w_{j-1})
+  int flush_now;
 };
 
 // Everything a kernel needs about a plan, passed by value.
@@ -67,8 +81,9 @@ struct DevPlan {
   void* scratch;       // B * NS transform values
   // MINRES vectors, each B * N doubles
   double* V[3];
-  double* Z[2];
+  double* Z[kZSlots];  // slot zslot(j) holds the stored z_j
   double* W[2];
+  double* kcoef;       // per right-hand side, 3 x kBasis: coefficients of x_j, w_j, w_{j-1} on the basis
   double* R;
   MinresState* st;     // B entries
   double* partials;    // PART_KINDS * B * maxparts
@@ -141,7 +156,11 @@ __device__ __forceinline__ int xcd_remap(int w, int n) {
 enum StencilMode : int { STENCIL_PLAIN = 0, STENCIL_MINRES = 1, STENCIL_RESIDUAL = 2, STENCIL_REPORT = 3 };
 enum FwdMode : int { FWD_PLAIN = 0, FWD_LANCZOS = 1 };
 enum InvMode : int { INV_PLAIN = 0, INV_GAMMA_INIT = 1, INV_GAMMA_ITER = 2 };
-enum FinKind : int { FIN_BNORM = 0, FIN_DELTA = 1, FIN_GAMMA_INIT = 2, FIN_GAMMA_ITER = 3, FIN_RES = 4, FIN_REPORT = 5 };
+enum FinKind : int {
+  FIN_BNORM = 0, FIN_DELTA = 1, FIN_GAMMA_INIT = 2, FIN_GAMMA_ITER = 3, FIN_RES = 4, FIN_REPORT = 5,
+  FIN_RNORM = 6,   // stopping test on the recurrence residual; decides forming u
+  FIN_FINAL = 7    // end of a solve: form u if it is stale
+};
 
 // matvec decomposition: 256 spatial points per block and st_chunk forward time levels
 // (plus their mirrors) per block
@@ -163,6 +182,9 @@ hipError_t launch_update(const DevPlan& P, double* u, hipStream_t s);
 // identity preconditioner: z = r (mode 0), or the MINRES set-up / Lanczos step with
 // z = q and the partials of <q, q> (modes INV_GAMMA_INIT / INV_GAMMA_ITER)
 hipError_t launch_identity(const DevPlan& P, int mode, const double* in, double* out, hipStream_t s);
+// u (and at the flush w_j, w_{j-1}) from the resident basis, for right-hand sides whose
+// scalar step set form_now
+hipError_t launch_form(const DevPlan& P, double* u, hipStream_t s);
 // one block per right-hand side: fixed-order sum of the partials of a reduction and
 // the scalar step that consumes it
 hipError_t launch_fin(const DevPlan& P, int kind, double tol, int maxit, hipStream_t s);

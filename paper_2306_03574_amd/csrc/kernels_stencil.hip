@@ -141,7 +141,7 @@ __device__ __forceinline__ double stencil_run(const DevPlan& P, const double* __
 
 __global__ void __launch_bounds__(kStencilThreads)
 k_stencil(DevPlan P, int mode, const double* __restrict__ xin, double* __restrict__ yout,
-          const double* __restrict__ fref, int nparts_rnorm) {
+          const double* __restrict__ fref) {
   const int b = blockIdx.y;
   MinresState* st = P.st + b;
   const double* x = xin;
@@ -150,26 +150,12 @@ k_stencil(DevPlan P, int mode, const double* __restrict__ xin, double* __restric
   if (mode == STENCIL_MINRES) {
     if (st->state != ST_RUNNING) return;
     const int j = st->iter + 1;
-    x = P.Z[j & 1];
+    x = P.Z[zslot(j)];
     y = P.V[(j + 1) % 3];
     part_kind = PART_DELTA;
   } else if (mode == STENCIL_RESIDUAL) {
-    // stopping test on the recurrence residual of the update kernel (same fixed-order
-    // sum in every block); confirm explicitly when it passes
-    if (st->state != ST_RUNNING) return;
-    const double rn2 = sum_parts(part_slot(P, PART_RNORM, b), nparts_rnorm);
-    __shared__ int need_sh;
-    if (threadIdx.x == 0) {
-      const int need = (rn2 <= st->tol2 * st->bnorm2) || st->explicit_mode || st->iter >= st->maxit || st->lucky ||
-                       !(rn2 == rn2);
-      need_sh = need;
-      if (blockIdx.x == 0) {
-        st->rnorm2 = rn2;
-        st->need_check = need;
-      }
-    }
-    __syncthreads();
-    if (!need_sh) return;
+    // explicit residual only when the form kernel asked for a check
+    if (st->state != ST_RUNNING || !st->need_check) return;
   }
   x += (size_t)b * P.N;
   if (y) y += (size_t)b * P.N;
@@ -208,7 +194,8 @@ k_rhs(DevPlan P, const double* __restrict__ src, const double* __restrict__ psi0
   }
 }
 
-// Set-up of a solve: b = Y f into R and V_1, zero V_0, W_0, W_1 and u; ||b||^2 partials.
+// Set-up of a solve: b = Y f into R and V_1, zero V_0 and u; ||b||^2 partials.  (The w
+// vectors are written by the flush of the resident basis before they are first read.)
 __global__ void __launch_bounds__(kVecThreads)
 k_init(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
   const int b = blockIdx.y;
@@ -225,8 +212,6 @@ k_init(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
     P.R[off + e] = v;
     P.V[1][off + e] = v;
     P.V[0][off + e] = 0.0;
-    P.W[0][off + e] = 0.0;
-    P.W[1][off + e] = 0.0;
     u[off + e] = 0.0;
     acc += v * v;
   }
@@ -234,7 +219,8 @@ k_init(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
   if (threadIdx.x == 0) part_slot(P, PART_RNORM, b)[blockIdx.x] = bs;
 }
 
-// w_j = wa Z_j - wb w_{j-1} - wc w_{j-2};  x += xc w_j;  r = r1 r + r2 V_{j+1};  ||r||^2
+// Residual recurrence r = r1 r + r2 V_{j+1} and ||r||^2 partials; after the resident
+// basis (j > kBasis) also w_j = wa Z_j - wb w_{j-1} - wc w_{j-2} and x += xc w_j.
 __global__ void __launch_bounds__(kVecThreads)
 k_update(DevPlan P, double* __restrict__ u) {
   const int b = blockIdx.y;
@@ -243,27 +229,120 @@ k_update(DevPlan P, double* __restrict__ u) {
   const int j = st->iter;
   const double wa = st->wa, wb = st->wb, wc = st->wc, xc = st->xc, r1 = st->r1, r2 = st->r2;
   const size_t off = (size_t)b * P.N;
-  const double* __restrict__ Zj = P.Z[j & 1] + off;
-  const double* __restrict__ Wm1 = P.W[(j - 1) & 1] + off;
-  double* __restrict__ Wm2 = P.W[j & 1] + off;
   const double* __restrict__ Vn = P.V[(j + 1) % 3] + off;
   double* __restrict__ R = P.R + off;
-  double* __restrict__ X = u + off;
   const int nblk = gridDim.x;
   const size_t per = ((size_t)P.N + nblk - 1) / nblk;
   const size_t lo = (size_t)blockIdx.x * per;
   const size_t hi = lo + per < (size_t)P.N ? lo + per : (size_t)P.N;
   double acc = 0.0;
-  for (size_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-    const double w = wa * Zj[e] - wb * Wm1[e] - wc * Wm2[e];
-    Wm2[e] = w;
-    X[e] += xc * w;
-    const double r = r1 * R[e] + r2 * Vn[e];
-    R[e] = r;
-    acc += r * r;
+  if (j <= kBasis) {
+    for (size_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+      const double r = r1 * R[e] + r2 * Vn[e];
+      R[e] = r;
+      acc += r * r;
+    }
+  } else {
+    const double* __restrict__ Zj = P.Z[zslot(j)] + off;
+    const double* __restrict__ Wm1 = P.W[(j - 1) & 1] + off;
+    double* __restrict__ Wm2 = P.W[j & 1] + off;
+    double* __restrict__ X = u + off;
+    for (size_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+      const double w = wa * Zj[e] - wb * Wm1[e] - wc * Wm2[e];
+      Wm2[e] = w;
+      X[e] += xc * w;
+      const double r = r1 * R[e] + r2 * Vn[e];
+      R[e] = r;
+      acc += r * r;
+    }
   }
   const double bs = block_sum(acc);
   if (threadIdx.x == 0) part_slot(P, PART_RNORM, b)[blockIdx.x] = bs;
+}
+
+// u = sum_l xm_l Z_l over the first NB basis slots; with FLUSH also
+// W[kBasis & 1] = w_kBasis and W[(kBasis+1) & 1] = w_{kBasis-1} from their coefficients.
+template <int NB, bool FLUSH>
+__device__ __forceinline__ void form_from_basis(const DevPlan& P, int b, double* __restrict__ u) {
+  const size_t off = (size_t)b * P.N;
+  const double* kc = P.kcoef + (size_t)b * 3 * kBasis;
+  double cx[NB], c1[NB], c2[NB];
+  const double* zs[NB];
+#pragma unroll
+  for (int l = 0; l < NB; ++l) {
+    cx[l] = kc[l];
+    c1[l] = FLUSH ? kc[kBasis + l] : 0.0;
+    c2[l] = FLUSH ? kc[2 * kBasis + l] : 0.0;
+    zs[l] = P.Z[l] + off;
+  }
+  double* X = u + off;
+  double* W1 = P.W[kBasis & 1] + off;
+  double* W2 = P.W[(kBasis + 1) & 1] + off;
+  const int nblk = gridDim.x;
+  const size_t per = ((size_t)P.N + nblk - 1) / nblk;
+  const size_t lo = (size_t)blockIdx.x * per;
+  const size_t hi = lo + per < (size_t)P.N ? lo + per : (size_t)P.N;
+  // two elements per trip (the second clamped into range), so 2 NB loads are in flight
+  for (size_t e0 = lo + threadIdx.x; e0 < hi; e0 += 2 * (size_t)blockDim.x) {
+    const size_t e1 = e0 + blockDim.x;
+    const size_t e1c = e1 < hi ? e1 : e0;
+    double z0[NB], z1[NB];
+#pragma unroll
+    for (int l = 0; l < NB; ++l) {
+      z0[l] = zs[l][e0];
+      z1[l] = zs[l][e1c];
+    }
+    double ax0 = 0.0, a10 = 0.0, a20 = 0.0, ax1 = 0.0, a11 = 0.0, a21 = 0.0;
+#pragma unroll
+    for (int l = 0; l < NB; ++l) {
+      ax0 += cx[l] * z0[l];
+      ax1 += cx[l] * z1[l];
+      if (FLUSH) {
+        a10 += c1[l] * z0[l];
+        a20 += c2[l] * z0[l];
+        a11 += c1[l] * z1[l];
+        a21 += c2[l] * z1[l];
+      }
+    }
+    X[e0] = ax0;
+    if (FLUSH) {
+      W1[e0] = a10;
+      W2[e0] = a20;
+    }
+    if (e1 < hi) {
+      X[e1] = ax1;
+      if (FLUSH) {
+        W1[e1] = a11;
+        W2[e1] = a21;
+      }
+    }
+  }
+}
+
+template <bool FLUSH>
+__device__ __forceinline__ void form_dispatch(const DevPlan& P, int b, int nb, double* u) {
+  switch (nb) {
+#define ABAC_FORM_CASE(K) \
+    case K: form_from_basis<K, FLUSH>(P, b, u); break;
+    ABAC_FORM_CASE(1) ABAC_FORM_CASE(2) ABAC_FORM_CASE(3) ABAC_FORM_CASE(4) ABAC_FORM_CASE(5) ABAC_FORM_CASE(6)
+    ABAC_FORM_CASE(7) ABAC_FORM_CASE(8) ABAC_FORM_CASE(9) ABAC_FORM_CASE(10) ABAC_FORM_CASE(11) ABAC_FORM_CASE(12)
+#undef ABAC_FORM_CASE
+    default: break;
+  }
+}
+static_assert(kBasis == 12, "form_dispatch lists one case per basis size");
+
+// Forms u (and at the flush w_j, w_{j-1}) from the resident basis for the right-hand
+// sides whose scalar step (FIN_RNORM or FIN_FINAL) set form_now; the others return at
+// once.  Writes no solve state.
+__global__ void __launch_bounds__(kVecThreads)
+k_form(DevPlan P, double* __restrict__ u) {
+  const int b = blockIdx.y;
+  const MinresState* st = P.st + b;
+  if (!st->form_now) return;
+  const int nb = st->nbasis;
+  if (st->flush_now) form_dispatch<true>(P, b, nb, u);
+  else form_dispatch<false>(P, b, nb, u);
 }
 
 // Identity preconditioner (MINRES-I): z = q, with the Lanczos step fused in.
@@ -284,7 +363,7 @@ k_identity(DevPlan P, int mode, const double* __restrict__ in, double* __restric
   double acc = 0.0;
   if (mode == INV_GAMMA_INIT) {
     const double* __restrict__ q = P.V[1] + off;
-    double* __restrict__ z = P.Z[1] + off;
+    double* __restrict__ z = P.Z[zslot(1)] + off;
     for (size_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
       const double v = q[e];
       z[e] = v;
@@ -295,7 +374,7 @@ k_identity(DevPlan P, int mode, const double* __restrict__ in, double* __restric
     double* __restrict__ q = P.V[(j + 1) % 3] + off;
     const double* __restrict__ vj = P.V[j % 3] + off;
     const double* __restrict__ vjm1 = P.V[(j + 2) % 3] + off;
-    double* __restrict__ z = P.Z[(j + 1) & 1] + off;
+    double* __restrict__ z = P.Z[zslot(j + 1)] + off;
     const double cA = st->sig, cB = st->delta * st->sig, cC = st->gamma * st->sig_prev;
     for (size_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
       const double v = cA * q[e] - cB * vj[e] - cC * vjm1[e];
@@ -308,8 +387,10 @@ k_identity(DevPlan P, int mode, const double* __restrict__ in, double* __restric
   if (threadIdx.x == 0) part_slot(P, PART_GAMMA, b)[blockIdx.x] = bs;
 }
 
-// Lanczos coefficient gamma_{j+1} and the Givens QR update of iteration j.
-__device__ void step_gamma_iter(MinresState* st, double g2) {
+// Lanczos coefficient gamma_{j+1} and the Givens QR update of iteration j.  In the
+// basis phase the w and x recurrences run on coefficient vectors over the basis
+// slots (kc: x, w_j, w_{j-1}), the same arithmetic the classic phase does on vectors.
+__device__ void step_gamma_iter(MinresState* st, double* kc, double g2) {
   if (!(g2 >= 0.0) || !(g2 < 1e300)) {
     st->state = ST_DONE;
     st->status = -5;  // ABAC_EBREAKDOWN
@@ -344,6 +425,20 @@ __device__ void step_gamma_iter(MinresState* st, double g2) {
   st->gamma = gn;
   st->iter += 1;
   if (gn == 0.0) st->lucky = 1;
+  const int j = st->iter;
+  if (j <= kBasis) {
+    double* xm = kc;
+    double* m1 = kc + kBasis;
+    double* m2 = kc + 2 * kBasis;
+    for (int l = 0; l < j; ++l) {
+      const double w = (l == j - 1 ? st->wa : 0.0) - st->wb * m1[l] - st->wc * m2[l];
+      m2[l] = m1[l];
+      m1[l] = w;
+      xm[l] += st->xc * w;
+    }
+    st->nbasis = j;
+    st->basis_dirty = 1;
+  }
 }
 
 // Copy the state of right-hand side b into the next slot of the host-mapped ring
@@ -362,6 +457,20 @@ k_fin(DevPlan P, int kind, int nparts, double tol, int maxit) {
   const int b = blockIdx.x;
   MinresState* st = P.st + b;
   const bool posts = kind == FIN_GAMMA_INIT || kind == FIN_RES;   // end of set-up / of an iteration
+  if ((kind == FIN_RES || kind == FIN_REPORT) && threadIdx.x == 0 && st->form_now) {
+    st->basis_dirty = 0;   // the form kernel wrote the iterate into u
+    st->form_now = 0;
+    st->flush_now = 0;
+  }
+  if (kind == FIN_FINAL || (kind == FIN_RNORM && st->state != ST_RUNNING)) {
+    // a stopped solve (breakdown in this iteration, or the end of the solve) with a
+    // stale u forms it from the basis
+    if (threadIdx.x == 0) {
+      st->form_now = st->basis_dirty;
+      st->flush_now = 0;
+    }
+    return;
+  }
   if ((kind != FIN_BNORM && kind != FIN_REPORT && st->state != ST_RUNNING) || (kind == FIN_RES && !st->need_check)) {
     if (posts && threadIdx.x == 0) post_snapshot(P, b);
     return;
@@ -372,6 +481,7 @@ k_fin(DevPlan P, int kind, int nparts, double tol, int maxit) {
     case FIN_DELTA: pk = PART_DELTA; break;
     case FIN_GAMMA_INIT:
     case FIN_GAMMA_ITER: pk = PART_GAMMA; break;
+    case FIN_RNORM: pk = PART_RNORM; break;
     default: pk = PART_RES; break;
   }
   const double tot = sum_parts(part_slot(P, pk, b), nparts);
@@ -386,6 +496,10 @@ k_fin(DevPlan P, int kind, int nparts, double tol, int maxit) {
       st->need_check = 0;
       st->lucky = 0;
       st->snap = 0;
+      st->nbasis = 0;
+      st->basis_dirty = 0;   // u = 0 = x_0
+      st->form_now = 0;
+      st->flush_now = 0;
       st->rnorm2 = tot;
       st->res2 = tot;
       st->status = 0;
@@ -414,10 +528,22 @@ k_fin(DevPlan P, int kind, int nparts, double tol, int maxit) {
       st->c1 = 1.0; st->c2 = 1.0;
       st->s1 = 0.0; st->s2 = 0.0;
       st->iter = 0;
+      for (int l = 0; l < 3 * kBasis; ++l) P.kcoef[(size_t)b * 3 * kBasis + l] = 0.0;
       break;
     case FIN_GAMMA_ITER:
-      step_gamma_iter(st, tot);
+      step_gamma_iter(st, P.kcoef + (size_t)b * 3 * kBasis, tot);
       break;
+    case FIN_RNORM: {
+      // stopping test on the recurrence residual; the explicit residual confirms it
+      const int j = st->iter;
+      const int need = (tot <= st->tol2 * st->bnorm2) || st->explicit_mode || j >= st->maxit || st->lucky ||
+                       !(tot == tot);
+      st->rnorm2 = tot;
+      st->need_check = need;
+      st->form_now = j <= kBasis && (need || j == kBasis);
+      st->flush_now = j == kBasis;
+      break;
+    }
     case FIN_RES:
       st->res2 = tot;
       if (tot <= st->tol2 * st->bnorm2) {
@@ -457,7 +583,7 @@ int update_blocks(const DevPlan& P) {
 
 hipError_t launch_stencil(const DevPlan& P, int mode, const double* x, double* y, const double* f, hipStream_t s) {
   dim3 grid(stencil_grid(P, mode), P.B);
-  hipLaunchKernelGGL(k_stencil, grid, dim3(kStencilThreads), 0, s, P, mode, x, y, f, update_blocks(P));
+  hipLaunchKernelGGL(k_stencil, grid, dim3(kStencilThreads), 0, s, P, mode, x, y, f);
   return hipGetLastError();
 }
 
@@ -484,6 +610,12 @@ hipError_t launch_update(const DevPlan& P, double* u, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_form(const DevPlan& P, double* u, hipStream_t s) {
+  dim3 grid(update_blocks(P), P.B);
+  hipLaunchKernelGGL(k_form, grid, dim3(kVecThreads), 0, s, P, u);
+  return hipGetLastError();
+}
+
 hipError_t launch_identity(const DevPlan& P, int mode, const double* in, double* out, hipStream_t s) {
   dim3 grid(update_blocks(P), P.B);
   hipLaunchKernelGGL(k_identity, grid, dim3(kVecThreads), 0, s, P, mode, in, out);
@@ -493,7 +625,8 @@ hipError_t launch_identity(const DevPlan& P, int mode, const double* in, double*
 hipError_t launch_fin(const DevPlan& P, int kind, double tol, int maxit, hipStream_t s) {
   int nparts;
   switch (kind) {
-    case FIN_BNORM: nparts = update_blocks(P); break;
+    case FIN_BNORM:
+    case FIN_RNORM: nparts = update_blocks(P); break;
     case FIN_DELTA: nparts = stencil_grid(P, STENCIL_MINRES); break;
     case FIN_GAMMA_INIT:
     case FIN_GAMMA_ITER: nparts = P.gamma_nparts; break;

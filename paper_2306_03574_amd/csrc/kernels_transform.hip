@@ -242,21 +242,22 @@ k_dsty(DevPlan P, int check) {
   const int cp = cb * S + s;
   const bool valid = cp < cpairs;
   const int ld = P.Mx / 2;
-  C* col = reinterpret_cast<C*>(reinterpret_cast<T*>(P.scratch) + (size_t)b * P.NS + (size_t)t * P.ms) + cp;
+  C* col = reinterpret_cast<C*>(reinterpret_cast<T*>(P.scratch) + (size_t)b * P.NS + (size_t)t * P.ms) +
+           min(cp, cpairs - 1);   // clamped: the loads below are unconditional
   C v[R];
+  // odd extension of the column: element tt is x[tt-1] for 0 < tt < My, -x[2 My - tt - 1]
+  // for tt > My, 0 at tt = 0 and tt = My
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const int tt = j + i * TPS;
-    C z{0, 0};
-    if (valid) {
-      if (tt > 0 && tt < My) {
-        z = col[(size_t)(tt - 1) * ld];
-      } else if (tt > My) {
-        const C w = col[(size_t)(2 * My - tt - 1) * ld];
-        z = C{-w.x, -w.y};
-      }
-    }
-    v[i] = z;
+    const int src = tt < My ? max(tt - 1, 0) : min(2 * My - tt - 1, My - 2);
+    v[i] = col[(size_t)src * ld];
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int tt = j + i * TPS;
+    const bool zero = !valid || tt == 0 || tt == My;
+    v[i] = zero ? C{0, 0} : (tt < My ? v[i] : C{-v[i].x, -v[i].y});
   }
   stage_table(tws, reinterpret_cast<const C*>(P.twy), L);
   __syncthreads();
@@ -320,19 +321,23 @@ k_time(DevPlan P, int check) {
   const int npairs = P.ms / 2;
   const int pair = blockIdx.x * S + s;
   const bool valid = pair < npairs;
+  const int pc = min(pair, npairs - 1);   // clamped: the loads below are unconditional
   const int ld = npairs;
   C* g = reinterpret_cast<C*>(reinterpret_cast<T*>(P.scratch) + (size_t)b * P.NS) + pair;
+  const C* gin = reinterpret_cast<const C*>(reinterpret_cast<const T*>(P.scratch) + (size_t)b * P.NS) + pc;
   const T* __restrict__ beta = reinterpret_cast<const T*>(P.beta);
-  const T ba = valid ? beta[2 * pair] : (T)1;
-  const T bb = valid ? beta[2 * pair + 1] : (T)1;
+  const T ba = valid ? beta[2 * pc] : (T)1;
+  const T bb = valid ? beta[2 * pc + 1] : (T)1;
   C* my = lds + s;
   C v[R];
   // Y: e_t = g_{nt-1-t} (the D scaling follows once the table is in LDS)
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const int t = j + i * TPS;
-    v[i] = valid ? g[(size_t)(NT - 1 - t) * ld] : C{0, 0};
+    v[i] = gin[(size_t)(NT - 1 - t) * ld];
   }
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = valid ? v[i] : C{0, 0};
   stage_table(tws, reinterpret_cast<const C*>(P.twt), NT);
   stage_table(abk, reinterpret_cast<const C*>(P.abk), 2 * NT);
   stage_table(sc, reinterpret_cast<const T*>(P.sc), NT);
@@ -395,11 +400,11 @@ k_dstx_inv(DevPlan P, int mode, double* __restrict__ outp) {
   if (mode != INV_PLAIN) {
     if (st->state != ST_RUNNING) return;
     if (mode == INV_GAMMA_INIT) {
-      out = P.Z[1] + off;
+      out = P.Z[zslot(1)] + off;
       q = P.V[1] + off;
     } else {
       const int jj = st->iter + 1;
-      out = P.Z[(jj + 1) & 1] + off;
+      out = P.Z[zslot(jj + 1)] + off;
       q = P.V[(jj + 1) % 3] + off;
     }
   }
