@@ -10,7 +10,6 @@ Prints ONE JSON line on stdout (progress goes to stderr).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -110,13 +109,28 @@ def pmc_traffic(kernel_class, workload, prec):
 
 
 def source_sha():
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2306_03574_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(name.encode())
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2306_03574_amd.profiling import source_sha as sha
+    return sha()
+
+
+COPY_PROBE_BYTES = 1 << 30
+
+
+def copy_probe():
+    """A plain device copy of COPY_PROBE_BYTES (read and written once per dispatch):
+    the calibration run for the HBM byte counters.  Prints its own bandwidth."""
+    import torch
+    a = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = 5
+    for _ in range(n):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / n
+    print(json.dumps({"copy_bytes": COPY_PROBE_BYTES, "GB/s": round(2 * COPY_PROBE_BYTES / dt / 1e9, 1)}), flush=True)
 
 
 def run_gpu(w, prec, steps, warmup, tol, maxit, profile=True):
@@ -240,10 +254,14 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="serving: requests in the trace")
     ap.add_argument("--budget-gb", type=float, default=160.0, help="serving: HBM budget")
     ap.add_argument("--max-active", type=int, default=16, help="serving: concurrent solves")
+    ap.add_argument("--copy-probe", action="store_true", help="only run the HBM counter calibration copy")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the solver is single-GPU; see DESIGN.md for "
-              "how it would shard). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the solver runs on a single GPU and sharding one solve over "
+              "several GPUs is not implemented. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "serving_mix":
         run_serving(args)

@@ -1,0 +1,189 @@
+"""Summaries of rocprofv3 output for the committed profile records.
+
+    python -m paper_2306_03574_amd.profiling trace <trace_dir> <out.md> --command "..."
+    python -m paper_2306_03574_amd.profiling pmc <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir>
+            --copy-bytes B --workload NAME --prec fp64|fp32 --out-dir profiles --command "..." [--command ...]
+
+`trace` turns the kernel statistics of a `rocprofv3 --kernel-trace --stats` run into a
+short markdown table.  `pmc` turns two counter runs (`--pmc FETCH_SIZE`, then
+`--pmc WRITE_SIZE`) of the library and of a plain copy kernel of known size into HBM
+bytes per launch for each kernel of the library: the counters of the copy kernel give
+the factor that turns each counter into bytes (the copy reads and writes exactly
+`copy_bytes` per dispatch).  Each record carries the hash of the kernel sources it was
+taken on, so a later change of the kernels invalidates it.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+from collections import OrderedDict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# kernel symbol -> kernel class used by bench.py (k_stencil serves both the matvec and
+# the explicit residual, so its class is reported as "stencil" for both)
+CLASS_OF = OrderedDict([
+    ("k_stencil", "stencil"), ("k_dstx_fwd", "dstx_fwd"), ("k_dsty", "dsty"), ("k_time", "time"),
+    ("k_dstx_inv", "dstx_inv"), ("k_update", "update"), ("k_form", "form"), ("k_init", "init"),
+    ("k_rhs", "rhs"), ("k_fin", "fin"), ("k_identity", "identity"),
+])
+
+
+def source_sha() -> str:
+    """Hash of the HIP sources of the library (names and contents)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2306_03574_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(kernel_name: str) -> str:
+    """`void abac::(anonymous namespace)::k_time<double, 256, 64>(abac::DevPlan, int)` ->
+    `k_time<double, 256, 64>`."""
+    m = re.search(r"(k_\w+)(<[^>]*>)?", kernel_name)
+    return (m.group(1) + (m.group(2) or "")) if m else kernel_name.split("(")[0][:60]
+
+
+def _one(pattern: str) -> str:
+    hits = sorted(glob.glob(pattern, recursive=True))
+    if not hits:
+        raise FileNotFoundError(pattern)
+    return hits[0]
+
+
+def summarize_trace(trace_dir: str, out_md: str, command: str, note: str = "") -> list:
+    path = _one(os.path.join(trace_dir, "**", "*kernel_stats.csv"))
+    rows = list(csv.DictReader(open(path)))
+    lines = ["# Kernel statistics (rocprofv3 --kernel-trace --stats)", "",
+             f"Command (from the repository root, on one MI355X): `{command}`", ""]
+    if note:
+        lines += [note, ""]
+    lines += ["| kernel | calls | total ms | avg us | min us | max us | share |",
+              "|---|---:|---:|---:|---:|---:|---:|"]
+    out = []
+    for r in rows:
+        name = short_name(r["Name"])
+        calls = int(r["Calls"])
+        tot = float(r["TotalDurationNs"]) / 1e6
+        avg = float(r["AverageNs"]) / 1e3
+        mn = float(r["MinNs"]) / 1e3
+        mx = float(r["MaxNs"]) / 1e3
+        pct = float(r["Percentage"])
+        out.append(dict(kernel=name, calls=calls, total_ms=tot, avg_us=avg))
+        lines.append(f"| `{name}` | {calls} | {tot:.3f} | {avg:.2f} | {mn:.2f} | {mx:.2f} | {pct:.1f}% |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return out
+
+
+def _counter_means(run_dir: str, counter: str) -> dict:
+    """Mean counter value (KiB for the size counters) per dispatch, per kernel."""
+    path = _one(os.path.join(run_dir, "**", "*counter_collection.csv"))
+    per = OrderedDict()
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        key = short_name(r["Kernel_Name"])
+        d = per.setdefault(key, {"sum": 0.0, "n": 0, "grid": int(r["Grid_Size"])})
+        d["sum"] += float(r["Counter_Value"])
+        d["n"] += 1
+        d["grid"] = max(d["grid"], int(r["Grid_Size"]))
+    return {k: dict(mean=v["sum"] / v["n"], n=v["n"], grid=v["grid"]) for k, v in per.items()}
+
+
+def _copy_factor(run_dir: str, counter: str, copy_bytes: int) -> float:
+    """Bytes per counter unit: the largest-grid copy kernel moved `copy_bytes` per dispatch."""
+    path = _one(os.path.join(run_dir, "**", "*counter_collection.csv"))
+    best = None
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter or "copyBuffer" not in r["Kernel_Name"]:
+            continue
+        g = int(r["Grid_Size"])
+        if best is None or g > best[0]:
+            best = (g, [])
+        if g == best[0]:
+            best[1].append(float(r["Counter_Value"]))
+    if not best:
+        raise RuntimeError(f"no copy kernel in {run_dir}")
+    kib = sum(best[1]) / len(best[1])
+    return copy_bytes / (kib * 1024.0)
+
+
+def summarize_pmc(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, workload, prec, out_dir,
+                  commands):
+    fs = _copy_factor(copy_fetch_dir, "FETCH_SIZE", copy_bytes)
+    ws = _copy_factor(copy_write_dir, "WRITE_SIZE", copy_bytes)
+    fetch = _counter_means(fetch_dir, "FETCH_SIZE")
+    write = _counter_means(write_dir, "WRITE_SIZE")
+    sha = source_sha()
+    os.makedirs(out_dir, exist_ok=True)
+    lines = [f"# HBM traffic per launch, workload `{workload}`, {prec} transforms (rocprofv3 --pmc)", "",
+             "Commands (from the repository root, on one MI355X), each counter in a run of its own:", ""]
+    lines += [f"* `{c}`" for c in commands]
+    lines += ["", f"Calibration on a plain copy kernel of {copy_bytes} bytes per dispatch: bytes = "
+              f"{fs:.3f} x FETCH_SIZE(KiB) x 1024 for reads and {ws:.3f} x WRITE_SIZE(KiB) x 1024 for "
+              f"writes.  Averages are over every dispatch of the run (speculative iterations that exit "
+              f"at once included, as in the bench's per-launch figures).  Kernel sources: `{sha}`.", "",
+              "| kernel | dispatches | read MB/launch | write MB/launch | total MB/launch |",
+              "|---|---:|---:|---:|---:|"]
+    by_class = {}
+    for name, f in fetch.items():
+        w = write.get(name, {"mean": 0.0, "n": 0})
+        rb = f["mean"] * 1024.0 * fs
+        wb = w["mean"] * 1024.0 * ws
+        lines.append(f"| `{name}` | {f['n']} | {rb / 1e6:.2f} | {wb / 1e6:.2f} | {(rb + wb) / 1e6:.2f} |")
+        base = name.split("<")[0]
+        cls = CLASS_OF.get(base)
+        if cls:
+            c = by_class.setdefault(cls, {"bytes": 0.0, "n": 0, "kernels": []})
+            c["bytes"] += (rb + wb) * f["n"]
+            c["n"] += f["n"]
+            c["kernels"].append(name)
+    for cls, c in by_class.items():
+        rec = dict(kernel_class=cls, kernels=c["kernels"], workload=workload, prec=prec, dispatches=c["n"],
+                   bytes_per_launch=c["bytes"] / max(c["n"], 1), fetch_scale=fs, write_scale=ws,
+                   source_sha=sha, commands=commands)
+        with open(os.path.join(out_dir, f"pmc_{cls}_{workload}_{prec}.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+    with open(os.path.join(out_dir, f"pmc_{workload}_{prec}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return by_class
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("trace_dir")
+    t.add_argument("out_md")
+    t.add_argument("--command", required=True)
+    t.add_argument("--note", default="")
+    p = sub.add_parser("pmc")
+    for a in ("fetch_dir", "write_dir", "copy_fetch_dir", "copy_write_dir"):
+        p.add_argument(a)
+    p.add_argument("--copy-bytes", type=int, required=True)
+    p.add_argument("--workload", required=True)
+    p.add_argument("--prec", required=True)
+    p.add_argument("--out-dir", default=os.path.join(ROOT, "profiles"))
+    p.add_argument("--command", action="append", required=True)
+    a = ap.parse_args()
+    if a.cmd == "trace":
+        for r in summarize_trace(a.trace_dir, a.out_md, a.command, a.note):
+            print(f"{r['kernel']:40s} {r['calls']:6d} {r['avg_us']:10.2f} us")
+    else:
+        res = summarize_pmc(a.fetch_dir, a.write_dir, a.copy_fetch_dir, a.copy_write_dir, a.copy_bytes, a.workload,
+                            a.prec, a.out_dir, a.command)
+        for cls, c in res.items():
+            print(f"{cls:10s} {c['bytes'] / max(c['n'], 1) / 1e6:10.2f} MB/launch over {c['n']} dispatches")
+
+
+if __name__ == "__main__":
+    main()
