@@ -181,3 +181,26 @@ def apply_Pinv(g: Grid, alpha: float, y: np.ndarray, check_imag: bool = True, ab
         if imag > 1e-9 * scale:
             raise AssertionError(f"P^-1 y has a large imaginary part {imag:.3e} (scale {scale:.3e})")
     return z.real.copy()
+
+
+def apply_C_inv(g: Grid, alpha: float, y: np.ndarray, abar: float = 1.0) -> np.ndarray:
+    """z = C_alpha^{-1} y, the block alpha-circulant preconditioner itself (eqs.
+    (1.5)-(1.7), from the prior work the paper builds on): the three steps of Section
+    2.3 taken once, with the eigenvalues inverted instead of their inverse square roots:
+      Step 1: DST in space, D in time, DFT in time;
+      Step 2: multiply by mu^{-1};
+      Step 3: inverse DFT in time, D^{-1} in time, DST in space.
+    C_alpha is real, so the result is real up to rounding (asserted)."""
+    d = time_scaling(g.nt, alpha)
+    mu = mu_table(g, alpha, abar)
+    v = dst_space(np.asarray(y, dtype=np.float64), g)
+    v = _time_axis_scale(v, d)
+    v = np.fft.fft(v, axis=0)
+    v = v / mu
+    v = np.fft.ifft(v, axis=0)
+    v = _time_axis_scale(v, 1.0 / d)
+    z = dst_space(v.real, g) + 1j * dst_space(v.imag, g)
+    scale = max(np.max(np.abs(z.real)), 1e-300)
+    if np.max(np.abs(z.imag)) > 1e-9 * scale:
+        raise AssertionError("C_alpha^{-1} y has a large imaginary part")
+    return z.real.copy()
