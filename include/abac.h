@@ -111,6 +111,17 @@ abac_status abac_build_rhs(abac_plan *plan, const double *src, const double *psi
  * at level nt-1-k.  y must not alias x. */
 abac_status abac_apply_A(abac_plan *plan, const double *x, double *y);
 
+/* y = T x (eq. (1.2)) in natural time order (no reversal): (T x)^(k) = L (x^(k) +
+ * x^(k-2)) - 2 x^(k-1) (L_a with a variable coefficient).  y must not alias x. */
+abac_status abac_apply_T(abac_plan *plan, const double *x, double *y);
+
+/* z = C_alpha^{-1} r: the block alpha-circulant preconditioner itself (eqs.
+ * (1.5)-(1.7), the matrix of the prior work the paper starts from), computed as
+ * S [D^{-1} F^{-1} diag(mu^{-1}) F D] S: one spatial DST pair and one time FFT pair per
+ * mode, no time reversal.  With ABAC_PREC_NONE, z = r.  z may alias r.  Not allowed while
+ * a solve is in progress (ABAC_EINVAL). */
+abac_status abac_apply_Cinv(abac_plan *plan, const double *r, double *z);
+
 /* z = P_alpha^{-1} r = C_alpha^{-1/2} (C_alpha^{-1/2})^T r (eq. (1.9), Section 2.3),
  * computed as S [K Y K Y] S with S the orthonormal DST-I in space and
  * K = D^{-1} F^{-1} diag(mu^{-1/2}) F D per spatial mode in time (the transposed
@@ -143,6 +154,20 @@ abac_status abac_minres_advance(abac_plan *plan, int iterations);
 abac_status abac_minres_poll(abac_plan *plan, int *done);
 abac_status abac_minres_finish(abac_plan *plan, int *iters, double *relres, int *status);
 
+/* Restarted GMRES(restart) for the non-symmetric system T u = f with right
+ * preconditioning by C_alpha (the block alpha-circulant preconditioner, which is not
+ * symmetric and so needs a non-symmetric Krylov solver), x_0 = 0.  Stops at the first
+ * step whose rotated residual ||f - T u||_2 (equal to the true residual with right
+ * preconditioning) is <= tol ||f||_2, confirmed explicitly; a cycle of `restart` steps
+ * ends by forming u and restarting from its explicit residual.  f, u: [batch][nt][...]
+ * device vectors (u must not alias f); iters, relres, status: host arrays of batch
+ * entries (may be NULL).  1 <= restart <= 15 (the Arnoldi basis uses the plan's Krylov
+ * vectors).  Host-synchronous (one small device-to-host read per step).  Returns
+ * ABAC_OK, ABAC_ENOTCONV (some right-hand side reached maxit), ABAC_EBREAKDOWN
+ * (non-finite values) or ABAC_EINVAL. */
+abac_status abac_gmres_solve(abac_plan *plan, const double *f, double *u, double tol, int maxit, int restart,
+                             int *iters, double *relres, int *status);
+
 /* Kernel-time accounting (for roofline reports).  When enabled, every kernel the
  * plan launches is bracketed by HIP events on the plan stream.  read() synchronises
  * the stream and returns, for kernel class k (see ABAC_K_*), the summed duration in
@@ -159,7 +184,8 @@ enum {
   ABAC_K_RHS = 8,       /* right-hand side assembly                     */
   ABAC_K_FIN = 9,       /* per-RHS scalar steps (sums of partials)      */
   ABAC_K_FORM = 10,     /* stopping test; iterate from the resident basis */
-  ABAC_K_COUNT = 11
+  ABAC_K_GMRES = 11,    /* GMRES vector kernels (dots, axpys, scalings)  */
+  ABAC_K_COUNT = 12
 };
 abac_status abac_profile_enable(abac_plan *plan, int on);
 abac_status abac_profile_read(abac_plan *plan, int kernel, double *total_ms, long long *launches);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libabac.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, EBUDGET, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7
 PREC = {"fp64": 0, "fp32": 1, "none": 2}
 KERNELS = {"stencil": 0, "dstx_fwd": 1, "dsty": 2, "time": 3, "dstx_inv": 4, "update": 5,
-           "residual": 6, "init": 7, "rhs": 8, "fin": 9, "form": 10}
+           "residual": 6, "init": 7, "rhs": 8, "fin": 9, "form": 10, "gmres": 11}
 
 EXPORTED = [
     "abac_workspace_bytes", "abac_plan_create", "abac_plan_destroy", "abac_build_rhs", "abac_apply_A",
@@ -26,7 +26,8 @@ EXPORTED = [
     "abac_minres_finish", "abac_profile_enable", "abac_profile_read", "abac_profile_reset",
     "abac_status_string", "abac_last_error", "abac_fill_normal", "abac_server_create", "abac_server_destroy",
     "abac_server_submit", "abac_server_step", "abac_server_result", "abac_server_clock",
-    "abac_server_bytes_in_use", "abac_plan_tiles", "abac_plan_set_coefficient",
+    "abac_server_bytes_in_use", "abac_plan_tiles", "abac_plan_set_coefficient", "abac_apply_T", "abac_apply_Cinv",
+    "abac_gmres_solve",
 ]
 
 _lib = None
@@ -97,6 +98,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abac_server_clock.restype = D
     lib.abac_plan_tiles.argtypes = [P, ctypes.POINTER(I)]
     lib.abac_plan_tiles.restype = I
+    lib.abac_apply_T.argtypes = [P, VP, VP]
+    lib.abac_apply_T.restype = I
+    lib.abac_apply_Cinv.argtypes = [P, VP, VP]
+    lib.abac_apply_Cinv.restype = I
+    lib.abac_gmres_solve.argtypes = [P, VP, VP, D, I, I, VP, VP, VP]
+    lib.abac_gmres_solve.restype = I
     lib.abac_plan_set_coefficient.argtypes = [P, VP, VP, D]
     lib.abac_plan_set_coefficient.restype = I
     lib.abac_server_bytes_in_use.argtypes = [P]
@@ -193,6 +200,29 @@ class Plan:
         z = self.empty() if z is None else z
         _check(self._lib.abac_apply_Pinv(self._h, self._vec(r, "r"), self._vec(z, "z")), "abac_apply_Pinv")
         return z
+
+    def apply_T(self, x, y=None):
+        """y = T x (natural time order)."""
+        y = self.empty() if y is None else y
+        _check(self._lib.abac_apply_T(self._h, self._vec(x, "x"), self._vec(y, "y")), "abac_apply_T")
+        return y
+
+    def apply_Cinv(self, r, z=None):
+        """z = C_alpha^{-1} r (the block alpha-circulant preconditioner)."""
+        z = self.empty() if z is None else z
+        _check(self._lib.abac_apply_Cinv(self._h, self._vec(r, "r"), self._vec(z, "z")), "abac_apply_Cinv")
+        return z
+
+    def gmres(self, f, u=None, tol: float = 1e-8, maxit: int = 500, restart: int = 15):
+        """Right-preconditioned GMRES(restart) on T u = f.  Returns (u, iters, relres, status)."""
+        u = self.empty() if u is None else u
+        iters = (ctypes.c_int * self.batch)()
+        relres = (ctypes.c_double * self.batch)()
+        status = (ctypes.c_int * self.batch)()
+        _check(self._lib.abac_gmres_solve(self._h, self._vec(f, "f"), self._vec(u, "u"), float(tol), int(maxit),
+                                          int(restart), iters, relres, status), "abac_gmres_solve",
+               ok=(OK, ENOTCONV, EBREAKDOWN))
+        return u, list(iters), list(relres), list(status)
 
     def solve(self, f, u=None, tol: float = 1e-8, maxit: int = 500):
         """MINRES on Y T u = Y f.  Returns (u, iters[list], relres[list], status[list])."""

@@ -61,7 +61,8 @@ int default_wg(int kind, int L, int prec, int maxlds) {
 struct Layout {
   // vectors: V x3, Z x kZSlots, W x2, R
   static constexpr int kVecs = 3 + kZSlots + 2 + 1;
-  size_t twx, twy, twt, beta, abk, sc, sci, coef, scratch, vec[kVecs], kcoef, st, partials, counters, total;
+  size_t twx, twy, twt, beta, abk, sc, sci, coef, scratch, vec[kVecs], kcoef, gst, gflags, gparts, st, partials,
+      counters, total;
 };
 
 // Validate the problem and fill the size fields of a DevPlan.
@@ -135,6 +136,9 @@ Layout make_layout(const DevPlan& P, int prec) {
   Lo.scratch = take(prec == ABAC_PREC_NONE ? 0 : real * (size_t)P.NS * P.B);
   for (int i = 0; i < Layout::kVecs; ++i) Lo.vec[i] = take(sizeof(double) * (size_t)P.N * P.B);
   Lo.kcoef = take(sizeof(double) * 3 * kBasis * P.B);
+  Lo.gst = take(sizeof(GmresState) * P.B);
+  Lo.gflags = take(sizeof(GmresFlags) * P.B);
+  Lo.gparts = take(sizeof(double) * (size_t)(kGmresMax + 1) * kVecMaxBlocks * P.B);
   Lo.st = take(sizeof(MinresState) * P.B);
   Lo.partials = take(sizeof(double) * (size_t)P.maxparts * P.B * PART_KINDS);
   Lo.counters = take(sizeof(unsigned) * P.B);
@@ -212,6 +216,22 @@ abac_status enqueue_pinv(abac_plan* p, const double* r, double* z, int minres_mo
   const int inv_mode = minres_mode == 0 ? INV_PLAIN : (minres_mode == 1 ? INV_GAMMA_INIT : INV_GAMMA_ITER);
   RUN(ABAC_K_DSTX_INV, launch_dstx_inv(P, p->prec, inv_mode, z, p->stream));
   if (minres_mode) RUN(ABAC_K_FIN, launch_fin(P, minres_mode == 1 ? FIN_GAMMA_INIT : FIN_GAMMA_ITER, 0.0, 0, p->stream));
+  return ABAC_OK;
+}
+
+// z = C_alpha^{-1} r: the transform passes with the single time pass of weights
+// mu^{-1} (identity for ABAC_PREC_NONE).  z may alias r.
+abac_status enqueue_cinv(abac_plan* p, const double* r, double* z) {
+  const DevPlan& P = p->P;
+  if (p->prec == ABAC_PREC_NONE) {
+    RUN(ABAC_K_DSTX_INV, launch_identity(P, INV_PLAIN, r, z, p->stream));
+    return ABAC_OK;
+  }
+  RUN(ABAC_K_DSTX_FWD, launch_dstx_fwd(P, p->prec, FWD_PLAIN, 0, r, p->stream));
+  if (P.ny) RUN(ABAC_K_DSTY, launch_dsty(P, p->prec, 0, p->stream));
+  RUN(ABAC_K_TIME, launch_time(P, p->prec, 0, p->stream, 1));
+  if (P.ny) RUN(ABAC_K_DSTY, launch_dsty(P, p->prec, 0, p->stream));
+  RUN(ABAC_K_DSTX_INV, launch_dstx_inv(P, p->prec, INV_PLAIN, z, p->stream));
   return ABAC_OK;
 }
 
@@ -555,6 +575,9 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
   for (int i = 0; i < 2; ++i) P.W[i] = reinterpret_cast<double*>(base + Lo.vec[3 + kZSlots + i]);
   P.R = reinterpret_cast<double*>(base + Lo.vec[3 + kZSlots + 2]);
   P.kcoef = reinterpret_cast<double*>(base + Lo.kcoef);
+  P.gst = reinterpret_cast<GmresState*>(base + Lo.gst);
+  P.gflags = reinterpret_cast<GmresFlags*>(base + Lo.gflags);
+  P.gparts = reinterpret_cast<double*>(base + Lo.gparts);
   P.st = reinterpret_cast<MinresState*>(base + Lo.st);
   P.partials = reinterpret_cast<double*>(base + Lo.partials);
   P.counters = reinterpret_cast<unsigned*>(base + Lo.counters);
@@ -727,6 +750,96 @@ abac_status abac_apply_A(abac_plan* p, const double* x, double* y) {
 abac_status abac_apply_Pinv(abac_plan* p, const double* r, double* z) {
   if (!p || !r || !z) return fail(ABAC_EINVAL, "NULL argument");
   return enqueue_pinv(p, r, z, 0);
+}
+
+abac_status abac_apply_T(abac_plan* p, const double* x, double* y) {
+  if (!p || !x || !y) return fail(ABAC_EINVAL, "NULL argument");
+  if (x == y) return fail(ABAC_EINVAL, "y must not alias x");
+  RUN(ABAC_K_STENCIL, launch_stencil(p->P, STENCIL_T, x, y, nullptr, p->stream));
+  return ABAC_OK;
+}
+
+abac_status abac_apply_Cinv(abac_plan* p, const double* r, double* z) {
+  if (!p || !r || !z) return fail(ABAC_EINVAL, "NULL argument");
+  if (p->active) return fail(ABAC_EINVAL, "a solve is in progress on this plan");
+  return enqueue_cinv(p, r, z);
+}
+
+abac_status abac_gmres_solve(abac_plan* p, const double* f, double* u, double tol, int maxit, int restart,
+                             int* iters, double* relres, int* status) {
+  g_last_error.clear();
+  if (!p || !f || !u) return fail(ABAC_EINVAL, "NULL argument");
+  if (p->active) return fail(ABAC_EINVAL, "a solve is in progress on this plan");
+  if (!(tol > 0) || maxit < 1 || restart < 1 || restart > kGmresMax)
+    return fail(ABAC_EINVAL, "need tol > 0, maxit >= 1 and 1 <= restart <= " + std::to_string(kGmresMax));
+  if (f == u) return fail(ABAC_EINVAL, "u must not alias f");
+  const DevPlan& P = p->P;
+  const int B = P.B;
+  double* z = P.V[0];
+  double* w = P.V[1];
+  double* t = P.V[2];
+  std::vector<GmresFlags> fl(B);
+  auto read_flags = [&]() -> abac_status {
+    HIP_TRY(hipMemcpyAsync(fl.data(), P.gflags, sizeof(GmresFlags) * B, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return ABAC_OK;
+  };
+  auto any = [&](auto pred) {
+    for (const auto& x : fl)
+      if (pred(x)) return true;
+    return false;
+  };
+  RUN(ABAC_K_INIT, launch_ginit(P, f, u, p->stream));
+  RUN(ABAC_K_FIN, launch_gfin(P, G_INIT, tol, maxit, restart, p->stream));
+  RUN(ABAC_K_GMRES, launch_gbase(P, gslot(P, 0), u, 0, p->stream));
+  abac_status s = read_flags();
+  if (s != ABAC_OK) return s;
+  int j = 0;
+  // every running right-hand side takes the same steps (restarts happen at the end of
+  // a cycle, which all reach together), so one host-side column index serves all
+  while (any([](const GmresFlags& x) { return x.state == ST_RUNNING; })) {
+    s = enqueue_cinv(p, gslot(P, j), z);
+    if (s != ABAC_OK) return s;
+    RUN(ABAC_K_STENCIL, launch_stencil(P, STENCIL_T, z, w, nullptr, p->stream));
+    RUN(ABAC_K_GMRES, launch_gdots(P, j, w, p->stream));
+    RUN(ABAC_K_FIN, launch_gfin(P, G_DOTS1, 0.0, 0, 0, p->stream));
+    RUN(ABAC_K_GMRES, launch_gaxpy(P, j, 1, w, p->stream));
+    RUN(ABAC_K_GMRES, launch_gdots(P, j, w, p->stream));
+    RUN(ABAC_K_FIN, launch_gfin(P, G_DOTS2, 0.0, 0, 0, p->stream));
+    RUN(ABAC_K_GMRES, launch_gaxpy(P, j, 2, w, p->stream));
+    RUN(ABAC_K_FIN, launch_gfin(P, G_NORM, 0.0, 0, 0, p->stream));
+    RUN(ABAC_K_GMRES, launch_gnext(P, w, p->stream));
+    if ((s = read_flags()) != ABAC_OK) return s;
+    if (!any([](const GmresFlags& x) { return x.state == ST_RUNNING && x.need; })) {
+      ++j;
+      continue;
+    }
+    // form u = X0 + C^{-1}(V y) and check f - T u explicitly
+    RUN(ABAC_K_GMRES, launch_gcomb(P, j, t, p->stream));
+    s = enqueue_cinv(p, t, z);
+    if (s != ABAC_OK) return s;
+    RUN(ABAC_K_GMRES, launch_gaddx(P, u, z, p->stream));
+    RUN(ABAC_K_RESIDUAL, launch_stencil(P, STENCIL_RESVEC, u, t, f, p->stream));
+    RUN(ABAC_K_FIN, launch_gfin(P, G_CHECK, 0.0, 0, 0, p->stream));
+    RUN(ABAC_K_GMRES, launch_gbase(P, t, u, 1, p->stream));
+    if ((s = read_flags()) != ABAC_OK) return s;
+    const bool restarted = any([](const GmresFlags& x) { return x.state == ST_RUNNING && x.k == 0; });
+    j = restarted ? 0 : j + 1;
+    if (j >= restart) return fail(ABAC_EDEVICE, "GMRES cycle bookkeeping out of step");
+  }
+  std::vector<GmresState> h(B);
+  HIP_TRY(hipMemcpyAsync(h.data(), P.gst, sizeof(GmresState) * B, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  s = flush_prof(p);
+  if (s != ABAC_OK) return s;
+  abac_status worst = ABAC_OK;
+  for (int b = 0; b < B; ++b) {
+    if (iters) iters[b] = h[b].iter;
+    if (relres) relres[b] = h[b].bnorm2 > 0 ? std::sqrt(h[b].res2 / h[b].bnorm2) : 0.0;
+    if (status) status[b] = h[b].status;
+    if (h[b].status != ABAC_OK && (worst == ABAC_OK || h[b].status == ABAC_EBREAKDOWN)) worst = (abac_status)h[b].status;
+  }
+  return worst;
 }
 
 abac_status abac_minres_begin(abac_plan* p, const double* f, double* u, double tol, int maxit) {

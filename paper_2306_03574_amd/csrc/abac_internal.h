@@ -53,6 +53,30 @@ struct MinresState {
   int flush_now;
 };
 
+// vector kernels: 256 threads, about 16 elements per thread, at most 1024 blocks per
+// right-hand side (update_blocks)
+constexpr int kVecThreads = 256;
+constexpr int kVecPerThread = 16;
+constexpr int kVecMaxBlocks = 1024;
+
+// Restarted GMRES (right preconditioning with C_alpha^{-1}) on T u = f: per right-hand
+// side state.  The Arnoldi basis v_0 .. v_restart lives in the plan's Krylov vector
+// slots (so restart <= kGmresMax), H is the rotated Hessenberg matrix, column-major.
+constexpr int kGmresMax = 15;
+struct GmresState {
+  double H[(kGmresMax + 1) * kGmresMax];   // H[c * (kGmresMax + 1) + l]: row l, column c
+  double cs[kGmresMax], sn[kGmresMax];     // Givens rotations
+  double g[kGmresMax + 1];                 // rotated beta e_1
+  double y[kGmresMax];                     // least-squares solution (when forming u)
+  double h1[kGmresMax + 1], h2[kGmresMax + 1];   // the two Gram-Schmidt passes of a column
+  double bnorm2, tol2, scale, res2, resid2;
+  int iter, k, maxit, restart, state, status, need, explicit_mode, restart_now, pad_;
+};
+// what the host reads after every step
+struct GmresFlags {
+  int state, need, k, iter;
+};
+
 // Everything a kernel needs about a plan, passed by value.
 struct DevPlan {
   int nx, ny, nt, B;   // ny = 0 in 1D
@@ -84,6 +108,9 @@ struct DevPlan {
   double* Z[kZSlots];  // slot zslot(j) holds the stored z_j
   double* W[2];
   double* kcoef;       // per right-hand side, 3 x kBasis: coefficients of x_j, w_j, w_{j-1} on the basis
+  GmresState* gst;     // B entries (GMRES solves)
+  GmresFlags* gflags;  // B entries
+  double* gparts;      // B x (kGmresMax + 1) x kVecMaxBlocks partial dot products
   double* R;
   MinresState* st;     // B entries
   double* partials;    // PART_KINDS * B * maxparts
@@ -153,7 +180,12 @@ __device__ __forceinline__ int xcd_remap(int w, int n) {
 // ---------------------------------------------------------------------------
 // host-side launchers (defined in the kernel translation units)
 // ---------------------------------------------------------------------------
-enum StencilMode : int { STENCIL_PLAIN = 0, STENCIL_MINRES = 1, STENCIL_RESIDUAL = 2, STENCIL_REPORT = 3 };
+// PLAIN: y = Y T x; MINRES: the Lanczos matvec with <Y T z, z>; RESIDUAL: ||f - T u||^2
+// when the solve asked for a check; REPORT: ||f - T u||^2 always; T: y = T x (natural
+// time order); RESVEC: y = f - T x and its squared norm (partials in PART_RES)
+enum StencilMode : int {
+  STENCIL_PLAIN = 0, STENCIL_MINRES = 1, STENCIL_RESIDUAL = 2, STENCIL_REPORT = 3, STENCIL_T = 4, STENCIL_RESVEC = 5
+};
 enum FwdMode : int { FWD_PLAIN = 0, FWD_LANCZOS = 1 };
 enum InvMode : int { INV_PLAIN = 0, INV_GAMMA_INIT = 1, INV_GAMMA_ITER = 2 };
 enum FinKind : int {
@@ -182,6 +214,19 @@ hipError_t launch_update(const DevPlan& P, double* u, hipStream_t s);
 // identity preconditioner: z = r (mode 0), or the MINRES set-up / Lanczos step with
 // z = q and the partials of <q, q> (modes INV_GAMMA_INIT / INV_GAMMA_ITER)
 hipError_t launch_identity(const DevPlan& P, int mode, const double* in, double* out, hipStream_t s);
+
+// GMRES steps (kernels_gmres.hip); gslot(l) is the vector slot of Arnoldi vector v_l
+enum GmresFin : int { G_INIT = 0, G_DOTS1 = 1, G_DOTS2 = 2, G_NORM = 3, G_CHECK = 4 };
+hipError_t launch_ginit(const DevPlan& P, const double* f, double* u, hipStream_t s);
+hipError_t launch_gfin(const DevPlan& P, int kind, double tol, int maxit, int restart, hipStream_t s);
+hipError_t launch_gdots(const DevPlan& P, int j, const double* w, hipStream_t s);
+hipError_t launch_gaxpy(const DevPlan& P, int j, int pass, double* w, hipStream_t s);
+hipError_t launch_gnext(const DevPlan& P, const double* w, hipStream_t s);
+hipError_t launch_gbase(const DevPlan& P, const double* src, const double* u, int restart_step, hipStream_t s);
+hipError_t launch_gcomb(const DevPlan& P, int j, double* t, hipStream_t s);
+hipError_t launch_gaddx(const DevPlan& P, double* u, const double* z, hipStream_t s);
+__host__ __device__ inline double* gslot(const DevPlan& P, int l) { return l < kZSlots ? P.Z[l] : P.W[l - kZSlots]; }
+static_assert(kGmresMax + 1 <= kZSlots + 2, "the Arnoldi basis must fit the Z and W slots");
 // u (and at the flush w_j, w_{j-1}) from the resident basis, for right-hand sides whose
 // scalar step set form_now
 hipError_t launch_form(const DevPlan& P, double* u, hipStream_t s);
@@ -192,7 +237,8 @@ hipError_t launch_fin(const DevPlan& P, int kind, double tol, int maxit, hipStre
 // check != 0: skip right-hand sides whose solve is not running
 hipError_t launch_dstx_fwd(const DevPlan& P, int prec, int mode, int check, const double* in, hipStream_t s);
 hipError_t launch_dsty(const DevPlan& P, int prec, int check, hipStream_t s);
-hipError_t launch_time(const DevPlan& P, int prec, int check, hipStream_t s);
+// inv1 = 1: the single time pass of C_alpha^{-1} (mu^{-1}, no time reversal)
+hipError_t launch_time(const DevPlan& P, int prec, int check, hipStream_t s, int inv1 = 0);
 hipError_t launch_dstx_inv(const DevPlan& P, int prec, int mode, double* out, hipStream_t s);
 // transform kernel kinds (tile validity and LDS size differ per kind)
 enum TransformKind : int { TK_XFWD = 0, TK_XINV = 1, TK_Y = 2, TK_TIME = 3 };

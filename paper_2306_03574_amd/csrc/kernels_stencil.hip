@@ -12,9 +12,6 @@ namespace abac {
 
 namespace {
 
-constexpr int kVecThreads = 256;
-constexpr int kVecPerThread = 16;
-constexpr int kVecMaxBlocks = 1024;
 
 // Weights and neighbour offsets of L at one spatial point:
 //   (L s)_i = c s_i - w s_{i-1} - e s_{i+1} - so s_{i-nx} - no s_{i+nx}.
@@ -80,7 +77,11 @@ __device__ __forceinline__ double apply_L(const LCoef& q, const double* __restri
 // (RES: sum of squared residuals against f; DOT: <Y T x, x>).  The march keeps L of
 // the two previous levels in registers; every load is unconditional, so the loads of
 // a step (and of the unrolled next step) are all in flight together.
-template <bool RES, bool DOT>
+// what a matvec block writes: Y T x (time-reversed, the symmetrised operator), T x,
+// the residual vector f - T x, or only the squared residual norm
+enum StencilOut : int { OUT_REV = 0, OUT_NAT = 1, OUT_RESVEC = 2, OUT_RESNORM = 3 };
+
+template <int OUT, bool DOT>
 __device__ __forceinline__ double stencil_tile(const DevPlan& P, const double* __restrict__ x,
                                                double* __restrict__ y, const double* __restrict__ f, int tile,
                                                int chunk) {
@@ -110,10 +111,17 @@ __device__ __forceinline__ double stencil_tile(const DevPlan& P, const double* _
     const double out_f = Lk + Lf2 - 2.0 * zf1;          // (T x)_k
     const double zb2 = cb.c, Lb2 = L_of(q, cb);
     const double out_b = Lb0 + Lb2 - 2.0 * zb1;         // (T x)_kb, kb = n-1-k
-    if (RES) {
+    if (OUT == OUT_RESNORM || OUT == OUT_RESVEC) {
       const double rf = f[(size_t)k * m + i] - out_f;
       const double rb = f[(size_t)(n - 1 - k) * m + i] - out_b;
       acc += rf * rf + rb * rb;
+      if (OUT == OUT_RESVEC) {
+        y[(size_t)k * m + i] = rf;
+        y[(size_t)(n - 1 - k) * m + i] = rb;
+      }
+    } else if (OUT == OUT_NAT) {
+      y[(size_t)k * m + i] = out_f;
+      y[(size_t)(n - 1 - k) * m + i] = out_b;
     } else {
       y[(size_t)(n - 1 - k) * m + i] = out_f;           // Y reverses time
       y[(size_t)k * m + i] = out_b;
@@ -126,7 +134,7 @@ __device__ __forceinline__ double stencil_tile(const DevPlan& P, const double* _
 }
 
 // The blocks of one right-hand side (grid-stride, XCD-aware order).
-template <bool RES, bool DOT>
+template <int OUT, bool DOT>
 __device__ __forceinline__ double stencil_run(const DevPlan& P, const double* __restrict__ x, double* __restrict__ y,
                                               const double* __restrict__ f) {
   const int tiles = (P.m + kStencilThreads - 1) / kStencilThreads;
@@ -134,7 +142,7 @@ __device__ __forceinline__ double stencil_run(const DevPlan& P, const double* __
   double acc = 0.0;
   for (int w = blockIdx.x; w < nblk; w += gridDim.x) {
     const int lb = xcd_remap(w, nblk);
-    acc += stencil_tile<RES, DOT>(P, x, y, f, lb % tiles, lb / tiles);
+    acc += stencil_tile<OUT, DOT>(P, x, y, f, lb % tiles, lb / tiles);
   }
   return acc;
 }
@@ -162,12 +170,17 @@ k_stencil(DevPlan P, int mode, const double* __restrict__ xin, double* __restric
   const double* f = fref ? fref + (size_t)b * P.N : nullptr;
   double acc;
   if (mode == STENCIL_PLAIN) {
-    stencil_run<false, false>(P, x, y, f);
+    stencil_run<OUT_REV, false>(P, x, y, f);
+    return;
+  } else if (mode == STENCIL_T) {
+    stencil_run<OUT_NAT, false>(P, x, y, f);
     return;
   } else if (mode == STENCIL_MINRES) {
-    acc = stencil_run<false, true>(P, x, y, f);
+    acc = stencil_run<OUT_REV, true>(P, x, y, f);
+  } else if (mode == STENCIL_RESVEC) {
+    acc = stencil_run<OUT_RESVEC, false>(P, x, y, f);
   } else {
-    acc = stencil_run<true, false>(P, x, y, f);
+    acc = stencil_run<OUT_RESNORM, false>(P, x, y, f);
   }
   const double bs = block_sum(acc);
   if (threadIdx.x == 0) part_slot(P, part_kind, b)[blockIdx.x] = bs;

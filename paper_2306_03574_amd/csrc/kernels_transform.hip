@@ -282,9 +282,18 @@ k_dsty(DevPlan P, int check) {
 //   Z'_k = ((Ma + Mb) Z_k + (Ma - Mb) conj Z_{-k}) / 2.
 // mu is Hermitian in k (mu_{-k} = conj mu_k), so one thread handles the pair
 // (k, nt-k) with a single evaluation of Ma_k, Mb_k.  Input and output in LDS, natural
-// order; `scale` folds in the 1/nt of the inverse DFT.
+// order; `scale` folds in the 1/nt of the inverse DFT.  The weights are mu^{-1/2}
+// (ABAC factor) or, with inv1, mu^{-1} (the block alpha-circulant C_alpha^{-1}).
+// 1/mu (the weights of C_alpha^{-1} itself)
+template <typename T>
+__device__ __forceinline__ cplx<T> inv_complex(cplx<T> mu) {
+  const T g = (T)1 / (mu.x * mu.x + mu.y * mu.y);
+  return cplx<T>{mu.x * g, -mu.y * g};
+}
+
 template <typename T, int NT>
-__device__ __forceinline__ void spectral_pairs(cplx<T>* my, int S, int j, const cplx<T>* abk, T ba, T bb, T scale) {
+__device__ __forceinline__ void spectral_pairs(cplx<T>* my, int S, int j, const cplx<T>* abk, T ba, T bb, T scale,
+                                               int inv1) {
   using C = cplx<T>;
   constexpr int R = FftShape<NT>::R, TPS = NT / R;
   constexpr int NU = R / 2 + 1;
@@ -295,17 +304,20 @@ __device__ __forceinline__ void spectral_pairs(cplx<T>* my, int S, int j, const 
     const int kp = (NT - k) & (NT - 1);
     const C zk = my[k * S], zp = my[kp * S];
     const C A = abk[2 * k], Bk = abk[2 * k + 1];
-    const C Ma = inv_sqrt_principal<T>(C{A.x + ba * Bk.x, A.y + ba * Bk.y});
-    const C Mb = inv_sqrt_principal<T>(C{A.x + bb * Bk.x, A.y + bb * Bk.y});
+    const C mua = C{A.x + ba * Bk.x, A.y + ba * Bk.y}, mub = C{A.x + bb * Bk.x, A.y + bb * Bk.y};
+    const C Ma = inv1 ? inv_complex<T>(mua) : inv_sqrt_principal<T>(mua);
+    const C Mb = inv1 ? inv_complex<T>(mub) : inv_sqrt_principal<T>(mub);
     const C sp = cscale(cadd(Ma, Mb), scale), sm = cscale(csub(Ma, Mb), scale);
     my[k * S] = cadd(cmul(sp, zk), cmul(sm, cconj(zp)));
     if (kp != k) my[kp * S] = cadd(cmul(cconj(sp), zp), cmul(cconj(sm), cconj(zk)));
   }
 }
 
+// inv1 = 0: out = K Y K Y g with mu^{-1/2} (the ABAC P^{-1}); inv1 = 1: out = K g with
+// mu^{-1} and no time reversal (C_alpha^{-1} = S K S of eqs. (1.5)-(1.7)).
 template <typename T, int NT, int WG>
 __global__ void __launch_bounds__(WG)
-k_time(DevPlan P, int check) {
+k_time(DevPlan P, int check, int inv1) {
   using C = cplx<T>;
   constexpr int R = FftShape<NT>::R, TPS = NT / R, S = seqs_of<NT, WG>();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -330,11 +342,11 @@ k_time(DevPlan P, int check) {
   const T bb = valid ? beta[2 * pc + 1] : (T)1;
   C* my = lds + s;
   C v[R];
-  // Y: e_t = g_{nt-1-t} (the D scaling follows once the table is in LDS)
+  // Y (ABAC only): e_t = g_{nt-1-t}; the D scaling follows once the table is in LDS
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const int t = j + i * TPS;
-    v[i] = gin[(size_t)(NT - 1 - t) * ld];
+    v[i] = gin[(size_t)(inv1 ? t : NT - 1 - t) * ld];
   }
 #pragma unroll
   for (int i = 0; i < R; ++i) v[i] = valid ? v[i] : C{0, 0};
@@ -347,17 +359,18 @@ k_time(DevPlan P, int check) {
 #pragma unroll
   for (int i = 0; i < R; ++i) v[i] = cscale(v[i], sc[j + i * TPS]);
   const T half_inv_n = (T)(0.5 / NT);
+  const int reps = inv1 ? 1 : 2;
 #pragma unroll 1
-  for (int rep = 0; rep < 2; ++rep) {
+  for (int rep = 0; rep < reps; ++rep) {
     fft_seq<T, NT, false>(v, j, my, S, tw);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < R; ++i) my[(j + i * TPS) * S] = v[i];
     __syncthreads();
-    spectral_pairs<T, NT>(my, S, j, abk, ba, bb, half_inv_n);
+    spectral_pairs<T, NT>(my, S, j, abk, ba, bb, half_inv_n, inv1);
     __syncthreads();
     fft_seq<T, NT, true, true>(v, j, my, S, tw);
-    if (rep == 0) {
+    if (rep == 0 && reps == 2) {
       // D^{-1}, then Y, then D:  h_t = a^{2t-nt+1} c_{nt-1-t}
       __syncthreads();
 #pragma unroll
@@ -533,7 +546,7 @@ hipError_t launch_y_t(const DevPlan& P, int check, hipStream_t s) {
 }
 
 template <typename T, int NT, int WG>
-hipError_t launch_time_t(const DevPlan& P, int check, hipStream_t s) {
+hipError_t launch_time_t(const DevPlan& P, int check, int inv1, hipStream_t s) {
   if constexpr (!tile_ok<T, NT, WG, TK_TIME>()) {
     return hipErrorInvalidValue;
   } else {
@@ -541,7 +554,7 @@ hipError_t launch_time_t(const DevPlan& P, int check, hipStream_t s) {
     const int npairs = P.ms / 2;
     dim3 grid((npairs + S - 1) / S, P.B);
     const size_t lds = lds_of<T, NT, WG, TK_TIME>();
-    hipLaunchKernelGGL((k_time<T, NT, WG>), grid, dim3(WG), lds, s, P, check);
+    hipLaunchKernelGGL((k_time<T, NT, WG>), grid, dim3(WG), lds, s, P, check, inv1);
     return hipGetLastError();
   }
 }
@@ -594,8 +607,8 @@ hipError_t y_dispatch(const DevPlan& P, int check, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t time_dispatch(const DevPlan& P, int check, hipStream_t s) {
-#define CALL(LL, WW) launch_time_t<T, LL, WW>(P, check, s)
+hipError_t time_dispatch(const DevPlan& P, int check, int inv1, hipStream_t s) {
+#define CALL(LL, WW) launch_time_t<T, LL, WW>(P, check, inv1, s)
   ABAC_SWITCH_L(P.nt, P.wg_t, CALL)
 #undef CALL
 }
@@ -642,8 +655,8 @@ hipError_t launch_dsty(const DevPlan& P, int prec, int check, hipStream_t s) {
   return prec ? y_dispatch<float>(P, check, s) : y_dispatch<double>(P, check, s);
 }
 
-hipError_t launch_time(const DevPlan& P, int prec, int check, hipStream_t s) {
-  return prec ? time_dispatch<float>(P, check, s) : time_dispatch<double>(P, check, s);
+hipError_t launch_time(const DevPlan& P, int prec, int check, hipStream_t s, int inv1) {
+  return prec ? time_dispatch<float>(P, check, inv1, s) : time_dispatch<double>(P, check, inv1, s);
 }
 
 hipError_t launch_dstx_inv(const DevPlan& P, int prec, int mode, double* out, hipStream_t s) {
