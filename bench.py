@@ -32,7 +32,8 @@ WORKLOADS = {
     "wave1d_63x64": dict(nx=63, ny=0, nt=64, alpha=1e-3, batch=1, source="manufactured1d"),
     "serving_mix": dict(nx=0, ny=0, nt=0, alpha=0.0, batch=1, source="serving"),
 }
-KERNEL_CLASSES = ["stencil", "dstx_fwd", "dsty", "time", "dstx_inv", "update", "form", "residual", "init", "rhs", "fin"]
+KERNEL_CLASSES = ["stencil", "dstx_fwd", "dsty", "time", "dstx_inv", "update", "form", "residual", "init", "rhs", "fin",
+                  "gmres"]
 
 
 def log(msg):
@@ -96,6 +97,29 @@ def algorithmic_bytes(w, prec, iters_total, solves):
     }
 
 
+def algorithmic_bytes_gmres(w, prec, steps_total, applies, solves):
+    """Algorithmic HBM bytes of right-preconditioned GMRES with C_alpha^{-1}: `applies`
+    applications of C^{-1} (one per Arnoldi step plus one per formed iterate), one T
+    matvec per step (16 N), one explicit residual vector per formed iterate (read u
+    and f, write f - T u: 24 N).  C^{-1} passes: x-DST 8 N + s NS, y-DST 2 x 2 s NS,
+    time 2 s NS, inverse x-DST s NS + 8 N.  The Gram-Schmidt vector kernels are not
+    modelled (their bytes grow with the column index)."""
+    nx, ny, nt = w["nx"], w["ny"], w["nt"]
+    N = nt * nx * max(ny, 1)
+    NS = nt * (nx + 1) * max(ny, 1)
+    s = 8 if prec == "fp64" else 4
+    forms = applies - steps_total
+    return {
+        "stencil": 16 * N * steps_total,
+        "dstx_fwd": (8 * N + s * NS) * applies,
+        "dsty": 2 * (2 * s * NS) * applies if ny else 0,
+        "time": 2 * s * NS * applies,
+        "dstx_inv": (s * NS + 8 * N) * applies,
+        "residual": 24 * N * forms,
+        "init": 32 * N * solves,
+    }
+
+
 def pmc_traffic(kernel_class, workload, prec):
     """Per-launch HBM bytes from a committed rocprofv3 counter summary, if it was taken
     on the current kernel sources; else None."""
@@ -133,7 +157,7 @@ def copy_probe():
     print(json.dumps({"copy_bytes": COPY_PROBE_BYTES, "GB/s": round(2 * COPY_PROBE_BYTES / dt / 1e9, 1)}), flush=True)
 
 
-def run_gpu(w, prec, steps, warmup, tol, maxit, profile=True):
+def run_gpu(w, prec, steps, warmup, tol, maxit, profile=True, solver="minres", restart=15):
     """Time `steps` whole solves (production path: graph-replayed iterations, no
     per-kernel events), then, if `profile`, repeat the same steps with every kernel
     bracketed by HIP events on the plan stream to get per-kernel durations."""
@@ -148,9 +172,14 @@ def run_gpu(w, prec, steps, warmup, tol, maxit, profile=True):
     plan = Plan(w["nx"], w["ny"], w["nt"], T=1.0, alpha=w["alpha"], prec=prec, batch=w["batch"], device=dev)
     f = plan.empty()
     u = plan.empty()
+    def solve():
+        if solver == "gmres":
+            return plan.gmres(f, u, tol=tol, maxit=maxit, restart=restart)
+        return plan.solve(f, u, tol=tol, maxit=maxit)
+
     for i in range(warmup):
         plan.build_rhs(d_src, d_p0, d_p1, f)
-        plan.solve(f, u, tol=tol, maxit=maxit)
+        solve()
     torch.cuda.synchronize()
 
     def timed(n):
@@ -160,7 +189,7 @@ def run_gpu(w, prec, steps, warmup, tol, maxit, profile=True):
         for i in range(n):
             ts = time.perf_counter()
             plan.build_rhs(d_src, d_p0, d_p1, f)
-            last = plan.solve(f, u, tol=tol, maxit=maxit)
+            last = solve()
             lat.append(time.perf_counter() - ts)
             iters_total += sum(last[1])
         torch.cuda.synchronize()
@@ -182,7 +211,7 @@ def run_gpu(w, prec, steps, warmup, tol, maxit, profile=True):
                 prof=prof, prof_elapsed=prof_elapsed, prof_iters=prof_iters, u=u_host)
 
 
-def cpu_baseline(w, tol, maxit):
+def cpu_baseline(w, tol, maxit, solver="minres", restart=15):
     """The oracle, as it stands, on one whole solve of the same workload (first
     right-hand side only for batched workloads)."""
     from oracle.discretization import Grid, L_matrix
@@ -192,8 +221,13 @@ def cpu_baseline(w, tol, maxit):
     L = L_matrix(g)
     c0, t0 = time.process_time(), time.perf_counter()
     f = aao.build_rhs(g, src[0], p0[0], p1[0])
-    res = mr.minres(lambda v: aao.apply_A(g, v, L), lambda y: pc.apply_Pinv(g, w["alpha"], y),
-                    aao.reverse_time(f), tol=tol, maxit=maxit)
+    if solver == "gmres":
+        from oracle import gmres as gm
+        res = gm.gmres(lambda v: aao.apply_T(g, v, L), lambda y: pc.apply_C_inv(g, w["alpha"], y), f, tol=tol,
+                       maxit=maxit, restart=restart)
+    else:
+        res = mr.minres(lambda v: aao.apply_A(g, v, L), lambda y: pc.apply_Pinv(g, w["alpha"], y),
+                        aao.reverse_time(f), tol=tol, maxit=maxit)
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
     return dict(value=1.0 / wall, unit="solves/s", cores=max(1, int(round(cpu / wall))), kind="oracle",
@@ -255,6 +289,10 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=160.0, help="serving: HBM budget")
     ap.add_argument("--max-active", type=int, default=16, help="serving: concurrent solves")
     ap.add_argument("--copy-probe", action="store_true", help="only run the HBM counter calibration copy")
+    ap.add_argument("--solver", default="minres", choices=["minres", "gmres"],
+                    help="minres: Y T u = Y f with the ABAC preconditioner (the method); gmres: T u = f "
+                         "right-preconditioned by the block alpha-circulant C_alpha")
+    ap.add_argument("--restart", type=int, default=15, help="gmres: restart length (<= 15)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -270,7 +308,8 @@ def main():
     prec = args.prec or ("fp32" if args.workload == "wave2d_511x511x512" else "fp64")
     other = "fp32" if prec == "fp64" else "fp64"
     log(f"workload {args.workload} prec {prec} steps {args.steps} warmup {args.warmup}")
-    main_run = run_gpu(w, prec, args.steps, args.warmup, args.tol, args.maxit)
+    main_run = run_gpu(w, prec, args.steps, args.warmup, args.tol, args.maxit, solver=args.solver,
+                       restart=args.restart)
     log(f"{prec}: {args.steps / main_run['elapsed']:.2f} solves/s iters {main_run['iters'][:4]} "
         f"relres {max(main_run['relres']):.2e}")
     B = w["batch"]
@@ -280,8 +319,12 @@ def main():
 
     # roofline of the dominant kernel class over the timed region
     prof = main_run["prof"]
-    dom = max((k for k in prof if prof[k]["launches"] > 0), key=lambda k: prof[k]["ms"])
-    abytes = algorithmic_bytes(w, prec, main_run["prof_iters"], args.steps * B)
+    if args.solver == "gmres":
+        abytes = algorithmic_bytes_gmres(w, prec, main_run["prof_iters"], prof["time"]["launches"],
+                                         args.steps * B)
+    else:
+        abytes = algorithmic_bytes(w, prec, main_run["prof_iters"], args.steps * B)
+    dom = max((k for k in prof if prof[k]["launches"] > 0 and k in abytes), key=lambda k: prof[k]["ms"])
     launches = prof[dom]["launches"]
     avg_s = prof[dom]["ms"] / 1e3 / launches
     bytes_per_launch = abytes.get(dom, 0) / launches
@@ -302,21 +345,23 @@ def main():
         "dtype": "f64" if prec == "fp64" else "f64-krylov/f32-transforms", "data": "synthetic",
         "config": {"workload": args.workload, "nx": w["nx"], "ny": w["ny"], "nt": w["nt"], "T": 1.0,
                    "alpha": w["alpha"], "batch": B, "tol": args.tol, "precond_precision": prec,
-                   "source": w["source"]},
+                   "source": w["source"], "solver": args.solver if args.solver == "minres" else
+                   f"gmres({args.restart}) on T u = f, right preconditioner C_alpha"},
         "p50_ms": round(float(np.percentile(lat_ms, 50)), 3), "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
         "iters": main_run["iters"][:8], "relres_max": max(main_run["relres"]),
         "roofline": roofline, "kernels": kernel_table,
     }
     if not args.no_compare:
         log(f"comparison leg: {other}")
-        cmp_run = run_gpu(w, other, max(3, args.steps // 2), 1, args.tol, args.maxit, profile=False)
+        cmp_run = run_gpu(w, other, max(3, args.steps // 2), 1, args.tol, args.maxit, profile=False,
+                          solver=args.solver, restart=args.restart)
         cmp_val = max(3, args.steps // 2) * B / cmp_run["elapsed"]
         diff = float(np.max(np.abs(cmp_run["u"] - main_run["u"])) / np.max(np.abs(main_run["u"])))
         out[f"{other}_precond"] = {"value": round(cmp_val, 3), "unit": "solves/s", "iters": cmp_run["iters"][:8],
                                    "relres_max": max(cmp_run["relres"]), "rel_diff_vs_" + prec: diff}
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle solve on the host")
-        cb = cpu_baseline(w, args.tol, args.maxit)
+        cb = cpu_baseline(w, args.tol, args.maxit, args.solver, args.restart)
         err = float(np.max(np.abs(main_run["u"][0] - cb["x"])) / np.max(np.abs(cb["x"])))
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["value"] = round(cb["value"], 5)

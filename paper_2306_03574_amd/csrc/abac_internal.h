@@ -12,7 +12,7 @@ namespace abac {
 // last block of a reduction writes the new values.
 enum : int { ST_IDLE = 0, ST_RUNNING = 1, ST_DONE = 2 };
 constexpr int kSnapRing = 16;   // host snapshot slots per right-hand side
-constexpr size_t kMaxTransformLds = 128 * 1024;   // dynamic LDS per transform block
+constexpr size_t kMaxTransformLds = 152 * 1024;   // dynamic LDS per transform block (gfx950: 160 KB per workgroup, 8 KB kept for static LDS)
 
 // Resident Krylov basis: z_1 .. z_kBasis each keep a slot of their own, and the
 // iterate is formed from them (x_j = sum_l y_l z_l) only when a residual check, a
