@@ -292,22 +292,44 @@ __device__ __forceinline__ cplx<T> inv_complex(cplx<T> mu) {
 }
 
 template <typename T, int NT>
-__device__ __forceinline__ void spectral_pairs(cplx<T>* my, int S, int j, const cplx<T>* abk, T ba, T bb, T scale,
-                                               int inv1) {
+struct SpectralWeights {
+  static constexpr int NU = FftShape<NT>::R / 2 + 1;   // frequency slots of one thread
+  cplx<T> sp[NU], sm[NU];
+};
+
+// The weights (Ma + Mb)/2 and (Ma - Mb)/2 (times `scale`) of the frequencies
+// k = j + u TPS <= NT/2 this thread handles; they depend on the mode pair only, so both
+// passes of K Y K Y use the same ones.
+template <typename T, int NT>
+__device__ __forceinline__ void spectral_weights(SpectralWeights<T, NT>& W, int j, const cplx<T>* abk, T ba, T bb,
+                                                 T scale, int inv1) {
   using C = cplx<T>;
   constexpr int R = FftShape<NT>::R, TPS = NT / R;
-  constexpr int NU = R / 2 + 1;
-#pragma unroll 2
-  for (int u = 0; u < NU; ++u) {
-    const int k = j + u * TPS;
-    if (k > NT / 2 || (u == R / 2 && j != 0)) continue;
-    const int kp = (NT - k) & (NT - 1);
-    const C zk = my[k * S], zp = my[kp * S];
+#pragma unroll
+  for (int u = 0; u < SpectralWeights<T, NT>::NU; ++u) {
+    const int k = min(j + u * TPS, NT / 2);   // out-of-range slots are never applied
     const C A = abk[2 * k], Bk = abk[2 * k + 1];
     const C mua = C{A.x + ba * Bk.x, A.y + ba * Bk.y}, mub = C{A.x + bb * Bk.x, A.y + bb * Bk.y};
     const C Ma = inv1 ? inv_complex<T>(mua) : inv_sqrt_principal<T>(mua);
     const C Mb = inv1 ? inv_complex<T>(mub) : inv_sqrt_principal<T>(mub);
-    const C sp = cscale(cadd(Ma, Mb), scale), sm = cscale(csub(Ma, Mb), scale);
+    W.sp[u] = cscale(cadd(Ma, Mb), scale);
+    W.sm[u] = cscale(csub(Ma, Mb), scale);
+  }
+}
+
+// Apply the weights to the packed spectrum in LDS: Z'_k = sp Z_k + sm conj Z_{-k} and
+// the mirrored formula at -k (one thread per pair (k, nt-k)).
+template <typename T, int NT>
+__device__ __forceinline__ void spectral_apply(cplx<T>* my, int S, int j, const SpectralWeights<T, NT>& W) {
+  using C = cplx<T>;
+  constexpr int R = FftShape<NT>::R, TPS = NT / R;
+#pragma unroll
+  for (int u = 0; u < SpectralWeights<T, NT>::NU; ++u) {
+    const int k = j + u * TPS;
+    if (k > NT / 2 || (u == R / 2 && j != 0)) continue;
+    const int kp = (NT - k) & (NT - 1);
+    const C zk = my[k * S], zp = my[kp * S];
+    const C sp = W.sp[u], sm = W.sm[u];
     my[k * S] = cadd(cmul(sp, zk), cmul(sm, cconj(zp)));
     if (kp != k) my[kp * S] = cadd(cmul(cconj(sp), zp), cmul(cconj(sm), cconj(zk)));
   }
@@ -358,7 +380,8 @@ k_time(DevPlan P, int check, int inv1) {
   const C* tw = tws;
 #pragma unroll
   for (int i = 0; i < R; ++i) v[i] = cscale(v[i], sc[j + i * TPS]);
-  const T half_inv_n = (T)(0.5 / NT);
+  SpectralWeights<T, NT> W;
+  spectral_weights<T, NT>(W, j, abk, ba, bb, (T)(0.5 / NT), inv1);
   const int reps = inv1 ? 1 : 2;
 #pragma unroll 1
   for (int rep = 0; rep < reps; ++rep) {
@@ -367,7 +390,7 @@ k_time(DevPlan P, int check, int inv1) {
 #pragma unroll
     for (int i = 0; i < R; ++i) my[(j + i * TPS) * S] = v[i];
     __syncthreads();
-    spectral_pairs<T, NT>(my, S, j, abk, ba, bb, half_inv_n, inv1);
+    spectral_apply<T, NT>(my, S, j, W);
     __syncthreads();
     fft_seq<T, NT, true, true>(v, j, my, S, tw);
     if (rep == 0 && reps == 2) {
