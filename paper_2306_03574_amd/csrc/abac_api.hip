@@ -111,6 +111,7 @@ abac_status describe(int nx, int ny, int nt, double T, double alpha, int prec, i
   // re-read fewer warm-up levels, shorter ones give more blocks.  The rule depends on
   // the shape only (not on the batch), so a batched solve sums its partials in the
   // same order as a single one.
+  P.st_threads = std::min(kStencilThreads, (nx + 63) / 64 * 64);
   P.st_chunk = 32;
   while (P.st_chunk > 8 && stencil_blocks(P) < 512) P.st_chunk /= 2;
   P.maxparts = std::max(stencil_blocks(P), std::max(update_blocks(P), (P.nt * P.ny1 + 1) / 2));

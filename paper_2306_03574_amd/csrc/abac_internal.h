@@ -120,9 +120,9 @@ struct DevPlan {
   // workgroup sizes of the transform kernels (chosen by the plan's autotuner)
   int wg_x, wg_xi, wg_y, wg_t;
   int st_chunk;        // forward time levels per matvec block
+  int st_threads;      // columns (threads) per matvec block
   int gamma_nparts;    // partial sums of <q, P^{-1} q> per right-hand side
   int prec;            // 0 FP64 transforms, 1 FP32 transforms, 2 no preconditioner
-  int pad3_;
 };
 
 // ---------------------------------------------------------------------------
@@ -194,11 +194,14 @@ enum FinKind : int {
   FIN_FINAL = 7    // end of a solve: form u if it is stale
 };
 
-// matvec decomposition: 256 spatial points per block and st_chunk forward time levels
-// (plus their mirrors) per block
+// matvec decomposition: a block covers a band of kStencilRows grid rows (one row in 1D)
+// times st_threads columns (64 <= st_threads <= 256), and st_chunk forward time levels
+// (plus their mirrors)
 constexpr int kStencilThreads = 256;
+constexpr int kStencilRows = 4;
 __host__ __device__ inline int stencil_blocks(const DevPlan& P) {
-  const int tiles = (P.m + kStencilThreads - 1) / kStencilThreads;
+  const int rb = P.ny ? kStencilRows : 1;
+  const int tiles = ((P.ny1 + rb - 1) / rb) * ((P.nx + P.st_threads - 1) / P.st_threads);
   const int nchunks = (P.nt / 2 + P.st_chunk - 1) / P.st_chunk;
   return tiles * nchunks;
 }

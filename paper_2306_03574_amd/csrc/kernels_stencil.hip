@@ -72,118 +72,196 @@ __device__ __forceinline__ double apply_L(const LCoef& q, const double* __restri
   return L_of(q, load5(q, lvl, i));
 }
 
-// One logical block of the matvec: spatial tile `tile`, forward levels [k0, k1) and
-// their mirrors nt-1-k.  Returns this thread's contribution to the fused reduction
-// (RES: sum of squared residuals against f; DOT: <Y T x, x>).  The march keeps L of
-// the two previous levels in registers; every load is unconditional, so the loads of
-// a step (and of the unrolled next step) are all in flight together.
 // what a matvec block writes: Y T x (time-reversed, the symmetrised operator), T x,
 // the residual vector f - T x, or only the squared residual norm
 enum StencilOut : int { OUT_REV = 0, OUT_NAT = 1, OUT_RESVEC = 2, OUT_RESNORM = 3 };
 
-template <int OUT, bool DOT>
+// One logical block of the matvec: a band of RB grid rows times st_threads consecutive
+// columns, forward levels [k0, k1) and their mirrors nt-1-k.  Each thread marches one
+// column of the band.  Per level it loads the RB+2 rows of its column (the band and the
+// two rows around it, clamped into the grid: a missing neighbour reads the centre with
+// weight 0, as in l_coef), so the y-neighbours of every row come from registers, and the
+// two x-neighbours of each row (L1 hits).  L of the two previous levels stays in
+// registers.  Every load is unconditional, so a step's loads are all in flight together.
+// VAR: variable coefficient, face weights per row; otherwise the x weights depend on the
+// column only and the y weights on the (block-uniform) row only.
+template <int RB, bool VAR>
+struct Band {
+  int rowoff[RB + 2];   // offsets of rows iy0-1 .. iy0+RB (clamped) at this column
+  int ow, oe;           // x-neighbour offsets of this column
+  double c[VAR ? RB : 1], w[VAR ? RB : 1], e[VAR ? RB : 1], so[VAR ? RB : 1], no[VAR ? RB : 1];
+  double cw, ce;        // constant coefficient: x weights of this column
+};
+
+template <int RB, bool VAR>
+__device__ __forceinline__ void band_level(const DevPlan& P, const Band<RB, VAR>& Bd, int iy0,
+                                           const double* __restrict__ lvl, double* L, double* z) {
+  double c[RB + 2], w[RB], e[RB];
+#pragma unroll
+  for (int r = 0; r < RB + 2; ++r) c[r] = lvl[Bd.rowoff[r]];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    w[r] = lvl[Bd.rowoff[r + 1] + Bd.ow];
+    e[r] = lvl[Bd.rowoff[r + 1] + Bd.oe];
+  }
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    if constexpr (VAR) {
+      L[r] = Bd.c[r] * c[r + 1] - (Bd.w[r] * w[r] + Bd.e[r] * e[r]) - (Bd.so[r] * c[r] + Bd.no[r] * c[r + 2]);
+    } else {
+      const int iy = iy0 + r;
+      const double so = P.ny && iy > 0 ? P.cy : 0.0;
+      const double no = P.ny && iy < P.ny - 1 ? P.cy : 0.0;
+      L[r] = P.c0 * c[r + 1] - (Bd.cw * w[r] + Bd.ce * e[r]) - (so * c[r] + no * c[r + 2]);
+    }
+    z[r] = c[r + 1];
+  }
+}
+
+template <int RB, bool VAR, int OUT, bool DOT>
 __device__ __forceinline__ double stencil_tile(const DevPlan& P, const double* __restrict__ x,
-                                               double* __restrict__ y, const double* __restrict__ f, int tile,
-                                               int chunk) {
-  const int n = P.nt, m = P.m;
-  const int i = tile * kStencilThreads + threadIdx.x;
-  if (i >= m) return 0.0;
-  const LCoef q = l_coef(P, i % P.nx, i / P.nx);   // loaded once, reused on every level
+                                               double* __restrict__ y, const double* __restrict__ f, int band,
+                                               int xt, int chunk) {
+  const int n = P.nt, m = P.m, nx = P.nx, ny1 = P.ny1;
+  const int ix_raw = xt * P.st_threads + threadIdx.x;
+  const bool active = ix_raw < nx;
+  const int ix = min(ix_raw, nx - 1);   // inactive lanes repeat the last column and store nothing
+  const int iy0 = band * RB;
+  Band<RB, VAR> Bd;
+#pragma unroll
+  for (int r = 0; r < RB + 2; ++r) Bd.rowoff[r] = min(max(iy0 - 1 + r, 0), ny1 - 1) * nx + ix;
+  Bd.ow = ix > 0 ? -1 : 0;
+  Bd.oe = ix < nx - 1 ? 1 : 0;
+  if constexpr (VAR) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const LCoef q = l_coef(P, ix, min(iy0 + r, ny1 - 1));
+      Bd.c[r] = q.c; Bd.w[r] = q.w; Bd.e[r] = q.e; Bd.so[r] = q.so; Bd.no[r] = q.no;
+    }
+  } else {
+    Bd.cw = ix > 0 ? P.cx : 0.0;
+    Bd.ce = ix < nx - 1 ? P.cx : 0.0;
+  }
   const int k0 = chunk * P.st_chunk;
   const int k1 = min(k0 + P.st_chunk, n / 2);
   double acc = 0.0;
-  // forward march state: x_{k-1} and L of x_{k-1}, x_{k-2} (zero before level 0); the
-  // loads come from a clamped level and are selected away, so they are unconditional
-  const int a2 = max(k0 - 2, 0), a1 = max(k0 - 1, 0);
-  const Lvl5 p2 = load5(q, x + (size_t)a2 * m, i), p1 = load5(q, x + (size_t)a1 * m, i);
-  double Lf2 = k0 >= 2 ? L_of(q, p2) : 0.0;
-  double zf1 = k0 >= 1 ? p1.c : 0.0, Lf1 = k0 >= 1 ? L_of(q, p1) : 0.0;
-  // backward march state at kb = n-1-k0: x_kb, x_{kb-1} and L of them
-  const int kb0 = n - 1 - k0;
-  double zb0 = x[(size_t)kb0 * m + i], Lb0 = apply_L(q, x + (size_t)kb0 * m, i);
-  double zb1 = x[(size_t)(kb0 - 1) * m + i], Lb1 = apply_L(q, x + (size_t)(kb0 - 1) * m, i);
-  // two levels per trip (chunks are even): both steps' loads are issued together
-#pragma unroll 2
-  for (int k = k0; k < k1; ++k) {
-    const Lvl5 cf = load5(q, x + (size_t)k * m, i);              // forward level k
-    const Lvl5 cb = load5(q, x + (size_t)(n - 3 - k) * m, i);    // backward level kb - 2
-    const double zk = cf.c, Lk = L_of(q, cf);
-    const double out_f = Lk + Lf2 - 2.0 * zf1;          // (T x)_k
-    const double zb2 = cb.c, Lb2 = L_of(q, cb);
-    const double out_b = Lb0 + Lb2 - 2.0 * zb1;         // (T x)_kb, kb = n-1-k
-    if (OUT == OUT_RESNORM || OUT == OUT_RESVEC) {
-      const double rf = f[(size_t)k * m + i] - out_f;
-      const double rb = f[(size_t)(n - 1 - k) * m + i] - out_b;
-      acc += rf * rf + rb * rb;
-      if (OUT == OUT_RESVEC) {
-        y[(size_t)k * m + i] = rf;
-        y[(size_t)(n - 1 - k) * m + i] = rb;
-      }
-    } else if (OUT == OUT_NAT) {
-      y[(size_t)k * m + i] = out_f;
-      y[(size_t)(n - 1 - k) * m + i] = out_b;
-    } else {
-      y[(size_t)(n - 1 - k) * m + i] = out_f;           // Y reverses time
-      y[(size_t)k * m + i] = out_b;
-      if (DOT) acc += out_f * zb0 + out_b * zk;
+  double Lf2[RB], zf1[RB], Lf1[RB], zb0[RB], Lb0[RB], zb1[RB], Lb1[RB], tL[RB], tz[RB];
+  {
+    // forward state before level k0 (zero before level 0: the clamped level's values
+    // are selected away); backward state at kb = n-1-k0 and kb-1
+    const int a2 = max(k0 - 2, 0), a1 = max(k0 - 1, 0);
+    band_level<RB, VAR>(P, Bd, iy0, x + (size_t)a2 * m, tL, tz);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) Lf2[r] = k0 >= 2 ? tL[r] : 0.0;
+    band_level<RB, VAR>(P, Bd, iy0, x + (size_t)a1 * m, tL, tz);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      Lf1[r] = k0 >= 1 ? tL[r] : 0.0;
+      zf1[r] = k0 >= 1 ? tz[r] : 0.0;
     }
-    Lf2 = Lf1; zf1 = zk; Lf1 = Lk;
-    zb0 = zb1; Lb0 = Lb1; zb1 = zb2; Lb1 = Lb2;
+    const int kb0 = n - 1 - k0;
+    band_level<RB, VAR>(P, Bd, iy0, x + (size_t)kb0 * m, Lb0, zb0);
+    band_level<RB, VAR>(P, Bd, iy0, x + (size_t)(kb0 - 1) * m, Lb1, zb1);
+  }
+  for (int k = k0; k < k1; ++k) {
+    double Lk[RB], zk[RB], Lb2[RB], zb2[RB];
+    band_level<RB, VAR>(P, Bd, iy0, x + (size_t)k * m, Lk, zk);               // forward level k
+    band_level<RB, VAR>(P, Bd, iy0, x + (size_t)(n - 3 - k) * m, Lb2, zb2);   // backward level kb - 2
+    double* yf = y + (size_t)k * m;
+    double* yb = y + (size_t)(n - 1 - k) * m;
+    const double* ff = f + (size_t)k * m;
+    const double* fb = f + (size_t)(n - 1 - k) * m;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const double out_f = Lk[r] + Lf2[r] - 2.0 * zf1[r];     // (T x)_k
+      const double out_b = Lb0[r] + Lb2[r] - 2.0 * zb1[r];    // (T x)_kb, kb = n-1-k
+      const int pos = Bd.rowoff[r + 1];
+      if (active && iy0 + r < ny1) {
+        if (OUT == OUT_RESNORM || OUT == OUT_RESVEC) {
+          const double rf = ff[pos] - out_f;
+          const double rb = fb[pos] - out_b;
+          acc += rf * rf + rb * rb;
+          if (OUT == OUT_RESVEC) {
+            yf[pos] = rf;
+            yb[pos] = rb;
+          }
+        } else if (OUT == OUT_NAT) {
+          yf[pos] = out_f;
+          yb[pos] = out_b;
+        } else {
+          yb[pos] = out_f;   // Y reverses time
+          yf[pos] = out_b;
+          if (DOT) acc += out_f * zb0[r] + out_b * zk[r];
+        }
+      }
+      Lf2[r] = Lf1[r]; zf1[r] = zk[r]; Lf1[r] = Lk[r];
+      zb0[r] = zb1[r]; Lb0[r] = Lb1[r]; zb1[r] = zb2[r]; Lb1[r] = Lb2[r];
+    }
   }
   return acc;
 }
 
-// The blocks of one right-hand side (grid-stride, XCD-aware order).
-template <int OUT, bool DOT>
-__device__ __forceinline__ double stencil_run(const DevPlan& P, const double* __restrict__ x, double* __restrict__ y,
-                                              const double* __restrict__ f) {
-  const int tiles = (P.m + kStencilThreads - 1) / kStencilThreads;
+// The blocks of one right-hand side (grid-stride, XCD-aware order: consecutive logical
+// blocks are neighbouring column tiles and bands of the same levels).
+template <int RB, bool VAR, int OUT, bool DOT>
+__device__ __forceinline__ double stencil_run_rb(const DevPlan& P, const double* __restrict__ x,
+                                                 double* __restrict__ y, const double* __restrict__ f) {
+  const int xtiles = (P.nx + P.st_threads - 1) / P.st_threads;
+  const int tiles = ((P.ny1 + RB - 1) / RB) * xtiles;
   const int nblk = stencil_blocks(P);
   double acc = 0.0;
   for (int w = blockIdx.x; w < nblk; w += gridDim.x) {
     const int lb = xcd_remap(w, nblk);
-    acc += stencil_tile<OUT, DOT>(P, x, y, f, lb % tiles, lb / tiles);
+    const int tile = lb % tiles;
+    acc += stencil_tile<RB, VAR, OUT, DOT>(P, x, y, f, tile / xtiles, tile % xtiles, lb / tiles);
   }
   return acc;
 }
 
+template <bool VAR, int OUT, bool DOT>
+__device__ __forceinline__ double stencil_run(const DevPlan& P, const double* __restrict__ x, double* __restrict__ y,
+                                              const double* __restrict__ f) {
+  return P.ny ? stencil_run_rb<kStencilRows, VAR, OUT, DOT>(P, x, y, f) : stencil_run_rb<1, VAR, OUT, DOT>(P, x, y, f);
+}
+
+// One kernel per mode and coefficient kind, so each gets the registers its own path
+// needs.
+template <int MODE, bool VAR>
 __global__ void __launch_bounds__(kStencilThreads)
-k_stencil(DevPlan P, int mode, const double* __restrict__ xin, double* __restrict__ yout,
-          const double* __restrict__ fref) {
+k_stencil(DevPlan P, const double* __restrict__ xin, double* __restrict__ yout, const double* __restrict__ fref) {
   const int b = blockIdx.y;
   MinresState* st = P.st + b;
   const double* x = xin;
   double* y = yout;
-  int part_kind = PART_RES;
-  if (mode == STENCIL_MINRES) {
+  if (MODE == STENCIL_MINRES) {
     if (st->state != ST_RUNNING) return;
     const int j = st->iter + 1;
     x = P.Z[zslot(j)];
     y = P.V[(j + 1) % 3];
-    part_kind = PART_DELTA;
-  } else if (mode == STENCIL_RESIDUAL) {
+  } else if (MODE == STENCIL_RESIDUAL) {
     // explicit residual only when the form kernel asked for a check
     if (st->state != ST_RUNNING || !st->need_check) return;
   }
   x += (size_t)b * P.N;
   if (y) y += (size_t)b * P.N;
   const double* f = fref ? fref + (size_t)b * P.N : nullptr;
-  double acc;
-  if (mode == STENCIL_PLAIN) {
-    stencil_run<OUT_REV, false>(P, x, y, f);
+  if (MODE == STENCIL_PLAIN) {
+    stencil_run<VAR, OUT_REV, false>(P, x, y, f);
     return;
-  } else if (mode == STENCIL_T) {
-    stencil_run<OUT_NAT, false>(P, x, y, f);
-    return;
-  } else if (mode == STENCIL_MINRES) {
-    acc = stencil_run<OUT_REV, true>(P, x, y, f);
-  } else if (mode == STENCIL_RESVEC) {
-    acc = stencil_run<OUT_RESVEC, false>(P, x, y, f);
-  } else {
-    acc = stencil_run<OUT_RESNORM, false>(P, x, y, f);
   }
+  if (MODE == STENCIL_T) {
+    stencil_run<VAR, OUT_NAT, false>(P, x, y, f);
+    return;
+  }
+  double acc;
+  if (MODE == STENCIL_MINRES)
+    acc = stencil_run<VAR, OUT_REV, true>(P, x, y, f);
+  else if (MODE == STENCIL_RESVEC)
+    acc = stencil_run<VAR, OUT_RESVEC, false>(P, x, y, f);
+  else
+    acc = stencil_run<VAR, OUT_RESNORM, false>(P, x, y, f);
   const double bs = block_sum(acc);
-  if (threadIdx.x == 0) part_slot(P, part_kind, b)[blockIdx.x] = bs;
+  if (threadIdx.x == 0) part_slot(P, MODE == STENCIL_MINRES ? PART_DELTA : PART_RES, b)[blockIdx.x] = bs;
 }
 
 // f_1 = tau^2 src_0 / 2 + tau psi1 + psi0; f_2 = tau^2 src_1 - L psi0; f_k = tau^2 src_{k-1}
@@ -596,7 +674,24 @@ int update_blocks(const DevPlan& P) {
 
 hipError_t launch_stencil(const DevPlan& P, int mode, const double* x, double* y, const double* f, hipStream_t s) {
   dim3 grid(stencil_grid(P, mode), P.B);
-  hipLaunchKernelGGL(k_stencil, grid, dim3(kStencilThreads), 0, s, P, mode, x, y, f);
+  const dim3 block(P.st_threads);
+#define ABAC_STENCIL_CASE(M)                                                                           \
+  case M:                                                                                              \
+    if (P.coef_x)                                                                                      \
+      hipLaunchKernelGGL((k_stencil<M, true>), grid, block, 0, s, P, x, y, f);                         \
+    else                                                                                               \
+      hipLaunchKernelGGL((k_stencil<M, false>), grid, block, 0, s, P, x, y, f);                        \
+    break;
+  switch (mode) {
+    ABAC_STENCIL_CASE(STENCIL_PLAIN)
+    ABAC_STENCIL_CASE(STENCIL_MINRES)
+    ABAC_STENCIL_CASE(STENCIL_RESIDUAL)
+    ABAC_STENCIL_CASE(STENCIL_REPORT)
+    ABAC_STENCIL_CASE(STENCIL_T)
+    ABAC_STENCIL_CASE(STENCIL_RESVEC)
+    default: return hipErrorInvalidValue;
+  }
+#undef ABAC_STENCIL_CASE
   return hipGetLastError();
 }
 
