@@ -71,11 +71,17 @@ size_t abac_workspace_bytes(int nx, int ny, int nt, int prec, int batch);
 abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int prec, int batch,
                              void *stream, void *workspace, size_t workspace_bytes, abac_plan **out);
 
-/* Workgroup sizes (threads) the plan's autotuner chose for its transform kernels:
- * wg[0] first x-DST pass, wg[1] y-DST pass, wg[2] time pass, wg[3] last x-DST pass.
- * The tuner times every legal tile on the plan's own buffers at creation and caches
- * the choice per shape (ABAC_TUNE=0 keeps 256-thread defaults; ABAC_TUNE_FILE names
- * an optional cache file). */
+/* Workgroup sizes (threads) of the plan's transform kernels, wg[0..4]:
+ * wg[0] first x-DST pass, wg[1] y-DST pass, wg[2] time pass, wg[3] last x-DST pass,
+ * wg[4] the fused x-y first and last passes, or 0 where the plan uses the separate
+ * passes.  The fused passes serve square 2D grids whose whole level fits in LDS: one
+ * workgroup per time level applies both spatial DSTs (Section 2.3's fast sine
+ * transforms) there, so the y passes over memory disappear; their tile and wg[3]
+ * follow fixed rules of the shape, since they carry the <q, P^{-1} q> sums
+ * (ABAC_SLAB=0 in the environment keeps the separate passes).  The other tiles are
+ * chosen by a tuner that times every legal tile on the plan's own buffers at creation
+ * and caches the choice per shape (ABAC_TUNE=0 keeps 256-thread defaults;
+ * ABAC_TUNE_FILE names an optional cache file).  wg must hold 5 ints. */
 abac_status abac_plan_tiles(abac_plan *plan, int *wg);
 
 /* Release the plan (synchronises its stream; frees library-owned memory only). */

@@ -285,10 +285,11 @@ class Plan:
             float(abar)), "abac_plan_set_coefficient")
 
     def tiles(self):
-        """Autotuned workgroup sizes: dict(dstx_fwd, dsty, time, dstx_inv)."""
-        wg = (ctypes.c_int * 4)()
+        """Workgroup sizes: dict(dstx_fwd, dsty, time, dstx_inv, slab); slab is the fused
+        x-y passes' workgroup, 0 when the plan uses separate x and y passes."""
+        wg = (ctypes.c_int * 5)()
         _check(self._lib.abac_plan_tiles(self._h, wg), "abac_plan_tiles")
-        return {"dstx_fwd": wg[0], "dsty": wg[1], "time": wg[2], "dstx_inv": wg[3]}
+        return {"dstx_fwd": wg[0], "dsty": wg[1], "time": wg[2], "dstx_inv": wg[3], "slab": wg[4]}
 
     # -- kernel timing -----------------------------------------------------------
     def profile(self, on: bool = True):

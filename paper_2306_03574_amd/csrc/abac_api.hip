@@ -210,12 +210,18 @@ abac_status enqueue_pinv(abac_plan* p, const double* r, double* z, int minres_mo
   const int check = minres_mode != 0;
   const int fwd_mode = minres_mode == 2 ? FWD_LANCZOS : FWD_PLAIN;
   const double* in = minres_mode == 1 ? P.V[1] : r;
-  RUN(ABAC_K_DSTX_FWD, launch_dstx_fwd(P, p->prec, fwd_mode, check, in, p->stream));
-  if (P.ny) RUN(ABAC_K_DSTY, launch_dsty(P, p->prec, check, p->stream));
-  RUN(ABAC_K_TIME, launch_time(P, p->prec, check, p->stream));
-  if (P.ny) RUN(ABAC_K_DSTY, launch_dsty(P, p->prec, check, p->stream));
   const int inv_mode = minres_mode == 0 ? INV_PLAIN : (minres_mode == 1 ? INV_GAMMA_INIT : INV_GAMMA_ITER);
-  RUN(ABAC_K_DSTX_INV, launch_dstx_inv(P, p->prec, inv_mode, z, p->stream));
+  if (P.wg_s) {
+    RUN(ABAC_K_DSTX_FWD, launch_dst2_fwd(P, p->prec, fwd_mode, check, in, p->stream));
+    RUN(ABAC_K_TIME, launch_time(P, p->prec, check, p->stream));
+    RUN(ABAC_K_DSTX_INV, launch_dst2_inv(P, p->prec, inv_mode, z, p->stream));
+  } else {
+    RUN(ABAC_K_DSTX_FWD, launch_dstx_fwd(P, p->prec, fwd_mode, check, in, p->stream));
+    if (P.ny) RUN(ABAC_K_DSTY, launch_dsty(P, p->prec, check, p->stream));
+    RUN(ABAC_K_TIME, launch_time(P, p->prec, check, p->stream));
+    if (P.ny) RUN(ABAC_K_DSTY, launch_dsty(P, p->prec, check, p->stream));
+    RUN(ABAC_K_DSTX_INV, launch_dstx_inv(P, p->prec, inv_mode, z, p->stream));
+  }
   if (minres_mode) RUN(ABAC_K_FIN, launch_fin(P, minres_mode == 1 ? FIN_GAMMA_INIT : FIN_GAMMA_ITER, 0.0, 0, p->stream));
   return ABAC_OK;
 }
@@ -226,6 +232,12 @@ abac_status enqueue_cinv(abac_plan* p, const double* r, double* z) {
   const DevPlan& P = p->P;
   if (p->prec == ABAC_PREC_NONE) {
     RUN(ABAC_K_DSTX_INV, launch_identity(P, INV_PLAIN, r, z, p->stream));
+    return ABAC_OK;
+  }
+  if (P.wg_s) {
+    RUN(ABAC_K_DSTX_FWD, launch_dst2_fwd(P, p->prec, FWD_PLAIN, 0, r, p->stream));
+    RUN(ABAC_K_TIME, launch_time(P, p->prec, 0, p->stream, 1));
+    RUN(ABAC_K_DSTX_INV, launch_dst2_inv(P, p->prec, INV_PLAIN, z, p->stream));
     return ABAC_OK;
   }
   RUN(ABAC_K_DSTX_FWD, launch_dstx_fwd(P, p->prec, FWD_PLAIN, 0, r, p->stream));
@@ -407,8 +419,11 @@ abac_status autotune(DevPlan& P, int prec, hipStream_t s, int maxlds) {
     }
     *field = best;
   };
-  pick(TK_XFWD, 2 * P.Mx, &P.wg_x, [&] { return launch_dstx_fwd(P, prec, FWD_LANCZOS, 1, nullptr, s); });
-  if (P.ny) pick(TK_Y, 2 * P.My, &P.wg_y, [&] { return launch_dsty(P, prec, 1, s); });
+  // (the fused 2D passes have a fixed tile; the separate x and y passes are not used)
+  if (!P.wg_s) {
+    pick(TK_XFWD, 2 * P.Mx, &P.wg_x, [&] { return launch_dstx_fwd(P, prec, FWD_LANCZOS, 1, nullptr, s); });
+    if (P.ny) pick(TK_Y, 2 * P.My, &P.wg_y, [&] { return launch_dsty(P, prec, 1, s); });
+  }
   pick(TK_TIME, P.nt, &P.wg_t, [&] { return launch_time(P, prec, 1, s); });
   // the last pass carries the <q, P^{-1} q> reduction: its tile stays at the fixed
   // default so the summation order (and the iterates) never depend on timing noise
@@ -547,6 +562,13 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
       P.wg_xi = wg;
   P.wg_y = ny ? default_wg(TK_Y, 2 * P.My, prec, maxlds) : 256;
   P.wg_t = default_wg(TK_TIME, nt, prec, maxlds);
+  // square 2D grids whose level fits in LDS take the fused x-y passes (a rule of the
+  // shape, since it fixes the order of the <q, p> sums); ABAC_SLAB=0 turns them off
+  {
+    const char* env = std::getenv("ABAC_SLAB");
+    const bool off = env && env[0] == '0';
+    P.wg_s = (prec == ABAC_PREC_NONE || off) ? 0 : slab_wg(nx, ny, prec, maxlds, 8192);
+  }
   if (prec != ABAC_PREC_NONE && (!P.wg_x || !P.wg_xi || !P.wg_y || !P.wg_t))
     return fail(ABAC_EINVAL, "transform does not fit the device LDS (" + std::to_string(maxlds) +
                                  " B); use the FP32 preconditioner for this size");
@@ -626,7 +648,7 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
     if (own) (void)hipFree(ws);
     return hip_fail(e, "table upload");
   }
-  P.gamma_nparts = prec == ABAC_PREC_NONE ? update_blocks(P) : dstx_blocks(P, P.wg_xi);
+  P.gamma_nparts = prec == ABAC_PREC_NONE ? update_blocks(P) : (P.wg_s ? P.nt : dstx_blocks(P, P.wg_xi));
   if (prec != ABAC_PREC_NONE) {
     abac_status ts = autotune(P, prec, static_cast<hipStream_t>(stream), maxlds);
     if (ts != ABAC_OK) {
@@ -989,6 +1011,7 @@ abac_status abac_plan_tiles(abac_plan* p, int* wg) {
   wg[1] = p->P.wg_y;
   wg[2] = p->P.wg_t;
   wg[3] = p->P.wg_xi;
+  wg[4] = p->P.wg_s;
   return ABAC_OK;
 }
 

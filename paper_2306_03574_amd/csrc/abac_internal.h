@@ -119,6 +119,7 @@ struct DevPlan {
   int maxparts;
   // workgroup sizes of the transform kernels (chosen by the plan's autotuner)
   int wg_x, wg_xi, wg_y, wg_t;
+  int wg_s;            // fused 2D passes (0: separate x and y passes)
   int st_chunk;        // forward time levels per matvec block
   int st_threads;      // columns (threads) per matvec block
   int gamma_nparts;    // partial sums of <q, P^{-1} q> per right-hand side
@@ -243,6 +244,10 @@ hipError_t launch_dsty(const DevPlan& P, int prec, int check, hipStream_t s);
 // inv1 = 1: the single time pass of C_alpha^{-1} (mu^{-1}, no time reversal)
 hipError_t launch_time(const DevPlan& P, int prec, int check, hipStream_t s, int inv1 = 0);
 hipError_t launch_dstx_inv(const DevPlan& P, int prec, int mode, double* out, hipStream_t s);
+// fused 2D first / last pass (square grids whose level fits in LDS; P.wg_s != 0)
+hipError_t launch_dst2_fwd(const DevPlan& P, int prec, int mode, int check, const double* in, hipStream_t s);
+hipError_t launch_dst2_inv(const DevPlan& P, int prec, int mode, double* out, hipStream_t s);
+int slab_wg(int nx, int ny, int prec, int maxlds, size_t margin);
 // transform kernel kinds (tile validity and LDS size differ per kind)
 enum TransformKind : int { TK_XFWD = 0, TK_XINV = 1, TK_Y = 2, TK_TIME = 3 };
 // dynamic LDS bytes of one workgroup (0 if the tile is not legal)

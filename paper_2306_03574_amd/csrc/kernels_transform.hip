@@ -523,6 +523,224 @@ k_dstx_inv(DevPlan P, int mode, double* __restrict__ outp) {
 }
 
 // ---------------------------------------------------------------------------
+// fused 2D passes, for square grids whose whole (y, x) level fits in LDS: one block
+// per time level applies the DST-I along x and along y in LDS, so the y passes over
+// HBM disappear (three transform passes per apply instead of five).  The level stays
+// in LDS as [ny][Mx] in the transform precision (column Mx-1 the zero pad, as in the
+// scratch layout, rows padded to Mx+1 entries so that the rows and the columns of
+// neighbouring sequences fall in different LDS banks); its lines go through a separate
+// exchange area, S sequences at a time.
+// ---------------------------------------------------------------------------
+template <typename T, int L>
+constexpr size_t slab_bytes() {
+  return ((size_t)(L / 2 - 1) * (L / 2 + 1) * sizeof(T) + 15) / 16 * 16;
+}
+
+template <typename T, int L, int WG>
+constexpr size_t slab_lds_of() {
+  return slab_bytes<T, L>() + (size_t)seqs_of<L, WG>() * L * sizeof(cplx<T>);
+}
+
+template <typename T, int L, int WG>
+constexpr bool slab_ok() {
+  return L >= 16 && L <= 256 && WG >= fft_tps<L>() && WG % fft_tps<L>() == 0 && WG % 64 == 0 &&
+         slab_lds_of<T, L, WG>() <= kMaxTransformLds;
+}
+
+// Orthonormal DST-I, in place, of `nlines` lines of the level held in LDS (ROWS: the
+// rows, element e of row l at slab[l (Mx+1) + e]; otherwise the columns, element e of
+// column l at slab[e (Mx+1) + l]).  Lines of length M-1 = L/2-1 go two to a complex
+// sequence of length L (odd extension); the transform of the first is minus the
+// imaginary part, of the second the real part.  Rows write 0 to the pad column.
+// All threads call it together; it ends with a barrier.
+template <typename T, int L, int WG, bool ROWS>
+__device__ __forceinline__ void slab_dst(T* slab, int nlines, cplx<T>* exch, const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_of<L, WG>(), M = L / 2, LD = M + 1;
+  const int s = threadIdx.x % S, j = threadIdx.x / S;
+  const int npairs = (nlines + 1) / 2;
+  const T scl = (T)(1.0 / sqrt((double)L));
+  for (int p0 = 0; p0 < npairs; p0 += S) {
+    const int p = p0 + s;
+    const bool va = 2 * p < nlines, vb = 2 * p + 1 < nlines;
+    const int la = min(2 * p, nlines - 1), lb = min(2 * p + 1, nlines - 1);
+    C v[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int t = j + i * TPS;
+      const int e = t < M ? max(t - 1, 0) : min(2 * M - t - 1, M - 2);
+      const T a = slab[ROWS ? la * LD + e : e * LD + la];
+      const T c = slab[ROWS ? lb * LD + e : e * LD + lb];
+      const bool zero = t == 0 || t == M;
+      const T sg = t < M ? (T)1 : (T)-1;
+      v[i] = C{zero || !va ? (T)0 : sg * a, zero || !vb ? (T)0 : sg * c};
+    }
+    __syncthreads();   // the previous round's last reads of the exchange area are done
+    fft_seq<T, L, false>(v, j, exch + s, S, tw);
+#pragma unroll
+    for (int i = 0; i <= R / 2; ++i) {
+      const int k = j + i * TPS;
+      if (k == 0 || k > M) continue;
+      if (k == M) {
+        if (ROWS) {
+          if (va) slab[la * LD + M - 1] = 0;
+          if (vb) slab[lb * LD + M - 1] = 0;
+        }
+        continue;
+      }
+      const int e = k - 1;
+      if (va) slab[ROWS ? la * LD + e : e * LD + la] = -v[i].y * scl;
+      if (vb) slab[ROWS ? lb * LD + e : e * LD + lb] = v[i].x * scl;
+    }
+  }
+  __syncthreads();
+}
+
+// first pass, fused: (Lanczos step,) DST-I along x and y of one level, level written
+// to the scratch.  Modes and checks as in k_dstx_fwd.
+template <typename T, int L, int WG>
+__global__ void __launch_bounds__(WG)
+k_dst2_fwd(DevPlan P, int mode, int check, const double* __restrict__ in) {
+  using C = cplx<T>;
+  constexpr int M = L / 2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* slab = reinterpret_cast<T*>(smem);
+  C* exch = reinterpret_cast<C*>(smem + slab_bytes<T, L>());
+  const int b = blockIdx.y, lvl = blockIdx.x;
+  const size_t off = (size_t)b * P.N;
+  const double* src = in ? in + off : nullptr;
+  double* qout = nullptr;
+  const double* vj = nullptr;
+  const double* vjm1 = nullptr;
+  double cA = 1.0, cB = 0.0, cC = 0.0;
+  if (check || mode == FWD_LANCZOS) {
+    const MinresState* st = P.st + b;
+    if (st->state != ST_RUNNING) return;
+    if (mode == FWD_LANCZOS) {
+      const int j = st->iter + 1;
+      qout = P.V[(j + 1) % 3] + off;
+      src = qout;
+      vj = P.V[j % 3] + off;
+      vjm1 = P.V[(j + 2) % 3] + off;
+      cA = st->sig;
+      cB = st->delta * st->sig;
+      cC = st->gamma * st->sig_prev;
+    }
+  }
+  const int nx = M - 1, cnt = nx * nx;
+  const size_t base = (size_t)lvl * P.m;
+  // stage the level; a thread's BATCH loads (clamped, so unconditional) are issued
+  // before any is used
+  constexpr int BATCH = 8;
+  for (int e0 = 0; e0 < cnt; e0 += BATCH * WG) {
+    double a[BATCH], bv[BATCH], cv[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const size_t e = base + min(e0 + (int)threadIdx.x + u * WG, cnt - 1);
+      a[u] = src[e];
+      if (mode == FWD_LANCZOS) {
+        bv[u] = vj[e];
+        cv[u] = vjm1[e];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int e = e0 + (int)threadIdx.x + u * WG;
+      if (e < cnt) {
+        double q = a[u];
+        if (mode == FWD_LANCZOS) {
+          q = cA * a[u] - cB * bv[u] - cC * cv[u];
+          qout[base + e] = q;
+        }
+        const int r = e / nx;
+        slab[r * (M + 1) + (e - r * nx)] = (T)q;
+      }
+    }
+  }
+  __syncthreads();
+  slab_dst<T, L, WG, true>(slab, nx, exch, reinterpret_cast<const C*>(P.twx));
+  slab_dst<T, L, WG, false>(slab, M, exch, reinterpret_cast<const C*>(P.twy));
+  T* out = reinterpret_cast<T*>(P.scratch) + (size_t)b * P.NS + (size_t)lvl * P.ms;
+  for (int e = threadIdx.x; e < nx * M; e += WG) {
+    const int r = e / M;
+    out[e] = slab[r * (M + 1) + (e - r * M)];
+  }
+}
+
+// last pass, fused: DST-I along y and x of one level of the scratch, FP64 rows out,
+// with the block's partial of <q, p> in MINRES modes (one partial per level).  Modes
+// as in k_dstx_inv.
+template <typename T, int L, int WG>
+__global__ void __launch_bounds__(WG)
+k_dst2_inv(DevPlan P, int mode, double* __restrict__ outp) {
+  using C = cplx<T>;
+  constexpr int M = L / 2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* slab = reinterpret_cast<T*>(smem);
+  C* exch = reinterpret_cast<C*>(smem + slab_bytes<T, L>());
+  const int b = blockIdx.y, lvl = blockIdx.x;
+  const size_t off = (size_t)b * P.N;
+  double* out = outp ? outp + off : nullptr;
+  const double* q = nullptr;
+  const MinresState* st = P.st + b;
+  if (mode != INV_PLAIN) {
+    if (st->state != ST_RUNNING) return;
+    if (mode == INV_GAMMA_INIT) {
+      out = P.Z[zslot(1)] + off;
+      q = P.V[1] + off;
+    } else {
+      const int jj = st->iter + 1;
+      out = P.Z[zslot(jj + 1)] + off;
+      q = P.V[(jj + 1) % 3] + off;
+    }
+  }
+  const int nx = M - 1, cnt = nx * M;
+  const T* scr = reinterpret_cast<const T*>(P.scratch) + (size_t)b * P.NS + (size_t)lvl * P.ms;
+  constexpr int BATCH = 16;
+  for (int e0 = 0; e0 < cnt; e0 += BATCH * WG) {
+    T v[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) v[u] = scr[min(e0 + (int)threadIdx.x + u * WG, cnt - 1)];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int e = e0 + (int)threadIdx.x + u * WG;
+      if (e < cnt) {
+        const int r = e / M;
+        slab[r * (M + 1) + (e - r * M)] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  slab_dst<T, L, WG, false>(slab, M, exch, reinterpret_cast<const C*>(P.twy));
+  slab_dst<T, L, WG, true>(slab, nx, exch, reinterpret_cast<const C*>(P.twx));
+  const size_t base = (size_t)lvl * P.m;
+  double* o = out + base;
+  const double* qq = q ? q + base : nullptr;
+  const int total = nx * nx;
+  double acc = 0.0;
+  for (int e0 = 0; e0 < total; e0 += BATCH * WG) {
+    double qv[BATCH];
+    if (qq) {
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) qv[u] = qq[min(e0 + (int)threadIdx.x + u * WG, total - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int e = e0 + (int)threadIdx.x + u * WG;
+      if (e < total) {
+        const int r = e / nx;
+        const double val = (double)slab[r * (M + 1) + (e - r * nx)];
+        o[e] = val;
+        if (qq) acc += val * qv[u];
+      }
+    }
+  }
+  if (mode == INV_PLAIN) return;
+  const double bs = block_sum(acc);
+  if (threadIdx.x == 0) part_slot(P, PART_GAMMA, b)[lvl] = bs;
+}
+
+// ---------------------------------------------------------------------------
 // launchers: one instantiation per (precision, length, workgroup size)
 // ---------------------------------------------------------------------------
 template <typename T, int L, int WG>
@@ -580,6 +798,48 @@ hipError_t launch_time_t(const DevPlan& P, int check, int inv1, hipStream_t s) {
     hipLaunchKernelGGL((k_time<T, NT, WG>), grid, dim3(WG), lds, s, P, check, inv1);
     return hipGetLastError();
   }
+}
+
+template <typename T, int L, int WG>
+hipError_t launch_slab_t(const DevPlan& P, bool fwd, int mode, int check, const double* in, double* out,
+                         hipStream_t s) {
+  if constexpr (!slab_ok<T, L, WG>()) {
+    return hipErrorInvalidValue;
+  } else {
+    dim3 grid(P.nt, P.B);
+    const size_t lds = slab_lds_of<T, L, WG>();
+    if (fwd)
+      hipLaunchKernelGGL((k_dst2_fwd<T, L, WG>), grid, dim3(WG), lds, s, P, mode, check, in);
+    else
+      hipLaunchKernelGGL((k_dst2_inv<T, L, WG>), grid, dim3(WG), lds, s, P, mode, out);
+    return hipGetLastError();
+  }
+}
+
+#define ABAC_SWITCH_SLAB(LVAR, WGVAR, CALL)                                               \
+  switch (LVAR) {                                                                         \
+    case 16: switch (WGVAR) { case 64: return CALL(16, 64); default: break; } break;      \
+    case 32: switch (WGVAR) { case 64: return CALL(32, 64); case 128: return CALL(32, 128); default: break; } break; \
+    case 64: switch (WGVAR) { case 128: return CALL(64, 128); case 256: return CALL(64, 256); default: break; } break; \
+    case 128: switch (WGVAR) { case 256: return CALL(128, 256); case 512: return CALL(128, 512); default: break; } break; \
+    case 256: switch (WGVAR) { case 256: return CALL(256, 256); case 512: return CALL(256, 512); default: break; } break; \
+    default: break;                                                                       \
+  }
+
+template <typename T>
+hipError_t slab_dispatch(const DevPlan& P, bool fwd, int mode, int check, const double* in, double* out,
+                         hipStream_t s) {
+#define CALL(LL, WW) launch_slab_t<T, LL, WW>(P, fwd, mode, check, in, out, s)
+  ABAC_SWITCH_SLAB(2 * P.Mx, P.wg_s, CALL)
+#undef CALL
+  return hipErrorInvalidValue;
+}
+
+template <typename T> size_t slab_lds_t(int L, int wg) {
+#define CALL(LL, WW) (slab_ok<T, LL, WW>() ? slab_lds_of<T, LL, WW>() : (size_t)0)
+  ABAC_SWITCH_SLAB(L, wg, CALL)
+#undef CALL
+  return 0;
 }
 
 #define ABAC_SWITCH_WG(WGVAR, CALL, LL)      \
@@ -684,6 +944,33 @@ hipError_t launch_time(const DevPlan& P, int prec, int check, hipStream_t s, int
 
 hipError_t launch_dstx_inv(const DevPlan& P, int prec, int mode, double* out, hipStream_t s) {
   return prec ? x_inv_dispatch<float>(P, mode, out, s) : x_inv_dispatch<double>(P, mode, out, s);
+}
+
+hipError_t launch_dst2_fwd(const DevPlan& P, int prec, int mode, int check, const double* in, hipStream_t s) {
+  return prec ? slab_dispatch<float>(P, true, mode, check, in, nullptr, s)
+              : slab_dispatch<double>(P, true, mode, check, in, nullptr, s);
+}
+
+hipError_t launch_dst2_inv(const DevPlan& P, int prec, int mode, double* out, hipStream_t s) {
+  return prec ? slab_dispatch<float>(P, false, mode, 0, nullptr, out, s)
+              : slab_dispatch<double>(P, false, mode, 0, nullptr, out, s);
+}
+
+// Workgroup of the fused 2D passes for this shape, or 0 where they do not apply (1D,
+// non-square grids, levels too large for LDS).  A fixed rule of the shape: the
+// largest instantiated workgroup whose sequences per round do not exceed the line
+// pairs of a level and whose LDS (plus `margin` for static LDS) fits `maxlds`.
+int slab_wg(int nx, int ny, int prec, int maxlds, size_t margin) {
+  if (!ny || nx != ny) return 0;
+  const int L = 2 * (nx + 1);
+  const int tps = transform_tps(L);
+  if (!tps) return 0;
+  for (int wg : {512, 256, 128, 64}) {
+    if (wg / tps > std::max((nx + 1) / 2, 64 / tps)) continue;
+    const size_t lds = prec ? slab_lds_t<float>(L, wg) : slab_lds_t<double>(L, wg);
+    if (lds && lds + margin <= (size_t)maxlds) return wg;
+  }
+  return 0;
 }
 
 bool transform_tile_valid(int kind, int L, int wg, int prec) {

@@ -1,0 +1,134 @@
+"""GPU: the fused x-y transform passes (one workgroup per time level applies both
+spatial DSTs in LDS) against the separate x and y passes and against the oracle.
+
+The fused passes are taken by square 2D grids whose level fits in LDS; ABAC_SLAB=0 at
+plan creation keeps the separate passes, so both routes run on the same inputs.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.discretization import Grid, L_matrix
+from oracle import allatonce as aao
+from oracle import preconditioner as pc
+from oracle import minres as mr
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _plan(nx, ny, nt, alpha=1e-3, prec="fp64", batch=1, slab=True, monkeypatch=None):
+    from paper_2306_03574_amd import Plan
+    print(f"[case] nx={nx} ny={ny} nt={nt} alpha={alpha} prec={prec} batch={batch} slab={slab}", flush=True)
+    monkeypatch.setenv("ABAC_SLAB", "1" if slab else "0")
+    return Plan(nx, ny, nt, T=1.0, alpha=alpha, prec=prec, batch=batch, device=DEV)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("nx,ny,prec,want", [
+    (7, 7, "fp64", True), (31, 31, "fp64", True), (63, 63, "fp64", True), (127, 127, "fp32", True),
+    (127, 127, "fp64", False), (255, 255, "fp32", False), (15, 7, "fp64", False), (63, 0, "fp64", False),
+])
+def test_which_plans_take_the_fused_passes(nx, ny, prec, want, monkeypatch):
+    p = _plan(nx, ny, 8, prec=prec, monkeypatch=monkeypatch)
+    assert (p.tiles()["slab"] > 0) == want
+    q = _plan(nx, ny, 8, prec=prec, slab=False, monkeypatch=monkeypatch)
+    assert q.tiles()["slab"] == 0
+
+
+CASES = [(7, 8, "fp64"), (15, 16, "fp64"), (31, 32, "fp64"), (63, 16, "fp64"), (31, 32, "fp32"), (63, 8, "fp32"),
+         (127, 8, "fp32")]
+
+
+@pytest.mark.parametrize("n,nt,prec", CASES)
+@pytest.mark.parametrize("op", ["Pinv", "Cinv"])
+def test_fused_passes_match_separate_passes(n, nt, prec, op, monkeypatch):
+    """Same operator either way: FP64 to rounding, FP32 to its own rounding level."""
+    r = np.random.default_rng(31).standard_normal((1, nt, n, n))
+    outs = []
+    for slab in (True, False):
+        p = _plan(n, n, nt, alpha=1e-2, prec=prec, slab=slab, monkeypatch=monkeypatch)
+        assert (p.tiles()["slab"] > 0) == slab
+        f = p.apply_Pinv if op == "Pinv" else p.apply_Cinv
+        outs.append(_host(f(_dev(r)))[0])
+    assert _rel(outs[0], outs[1]) < (1e-13 if prec == "fp64" else 2e-5)
+
+
+@pytest.mark.parametrize("n,nt,alpha", [(31, 32, 1e-1), (63, 16, 1e-3), (7, 8, 1e-3)])
+def test_fused_Pinv_fp64_matches_oracle(n, nt, alpha, monkeypatch):
+    g = Grid(n, n, nt, T=1.0)
+    r = np.random.default_rng(32).standard_normal(g.shape)
+    p = _plan(n, n, nt, alpha=alpha, monkeypatch=monkeypatch)
+    assert p.tiles()["slab"] > 0
+    z = _host(p.apply_Pinv(_dev(r[None])))[0]
+    assert _rel(z, pc.apply_Pinv(g, alpha, r)) < 1e-11
+
+
+@pytest.mark.parametrize("alpha", [1e-2, 1e-3])
+def test_fused_Pinv_fp32_127_matches_oracle(alpha, monkeypatch):
+    """127 x 127 level in FP32 (the batched 127^2 x 128 workload's shape), error ~ eps32 / alpha."""
+    n, nt = 127, 8
+    g = Grid(n, n, nt, T=1.0)
+    r = np.random.default_rng(33).standard_normal(g.shape)
+    p = _plan(n, n, nt, alpha=alpha, prec="fp32", monkeypatch=monkeypatch)
+    assert p.tiles()["slab"] > 0
+    z = _host(p.apply_Pinv(_dev(r[None])))[0]
+    assert _rel(z, pc.apply_Pinv(g, alpha, r)) < 50 * 6e-8 / alpha
+
+
+def test_fused_fixed_iterates_and_batch(monkeypatch):
+    """x_k after k iterations equals the oracle's; a batch of 3 equals three solo solves bitwise."""
+    n, nt, alpha, k = 31, 32, 1e-3, 4
+    g = Grid(n, n, nt)
+    fs = []
+    for seed in (41, 42, 43):
+        src, psi0, psi1 = synth.random_source(n, n, nt, seed=seed)
+        fs.append(aao.build_rhs(g, src, psi0, psi1))
+    L = L_matrix(g)
+    ref = mr.minres(lambda u: aao.apply_A(g, u, L), lambda y: pc.apply_Pinv(g, alpha, y),
+                    aao.reverse_time(fs[0]), fixed_iters=k)
+    p = _plan(n, n, nt, alpha=alpha, monkeypatch=monkeypatch)
+    u, iters, _, _ = p.solve(_dev(fs[0][None]), tol=1e-30, maxit=k)
+    assert iters == [k] and _rel(_host(u)[0], ref.x) < 1e-10
+    solo = []
+    for f in fs:
+        u, it, rr, _ = p.solve(_dev(f[None]), tol=1e-8, maxit=100)
+        solo.append((_host(u)[0], it[0], rr[0]))
+    pb = _plan(n, n, nt, alpha=alpha, batch=3, monkeypatch=monkeypatch)
+    ub, itb, rrb, stb = pb.solve(_dev(np.stack(fs)), tol=1e-8, maxit=100)
+    ubh = _host(ub)
+    for i in range(3):
+        assert np.array_equal(ubh[i], solo[i][0]) and itb[i] == solo[i][1] and rrb[i] == solo[i][2]
+
+
+def test_fused_fp32_solve_127(monkeypatch):
+    """FP32 preconditioner on 127^2 x 32 with a smoothed random source: converges to 1e-8
+    (explicit residual on the host) within two iterations of the FP64 preconditioner."""
+    n, nt, alpha = 127, 32, 1e-3
+    g = Grid(n, n, nt)
+    src, psi0, psi1 = synth.jacobi_smoothed_source(n, n, nt, seed=4000)
+    f = aao.build_rhs(g, src, psi0, psi1)
+    res = {}
+    for prec in ("fp32", "fp64"):
+        p = _plan(n, n, nt, alpha=alpha, prec=prec, monkeypatch=monkeypatch)
+        assert (p.tiles()["slab"] > 0) == (prec == "fp32")
+        u, iters, relres, status = p.solve(_dev(f[None]), tol=1e-8, maxit=100)
+        uh = _host(u)[0]
+        host_res = np.linalg.norm(f - aao.apply_T(g, uh)) / np.linalg.norm(f)
+        assert status == [0] and host_res <= 1e-8 * (1 + 1e-6)
+        res[prec] = iters[0]
+    assert abs(res["fp32"] - res["fp64"]) <= 2, res
