@@ -76,7 +76,7 @@ def gaussian_field_source(nx: int, ny: int, nt: int, T: float = 1.0, ell: float 
         kk = (k ** 2).reshape([-1 if a == ax else 1 for a in range(len(shape))])
         k2 = kk if k2 is None else k2 + kk
     spec *= np.exp(-2.0 * np.pi ** 2 * ell ** 2 * k2)
-    field = np.fft.irfftn(spec, s=shape)
+    field = np.fft.irfftn(spec, s=shape, axes=tuple(range(len(shape))))
     del spec
     field /= np.sqrt(np.mean(field ** 2))
     z = np.zeros(shape[1:])
