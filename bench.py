@@ -78,7 +78,7 @@ def algorithmic_bytes(w, prec, iters_total, solves):
                                read z, w1, w2, x; write w, x)
       form      8 (k+1) N      (read z_1..z_k, write u) once per solve of k <= 12
                                iterations (the convergence check)
-      init      40 N           (read f; write r, v1, v0, u) per solve
+      init      24 N           (read f; write v1 = r0, u) per solve
     """
     nx, ny, nt = w["nx"], w["ny"], w["nt"]
     N = nt * nx * max(ny, 1)
@@ -93,7 +93,7 @@ def algorithmic_bytes(w, prec, iters_total, solves):
         "dstx_inv": (s * NS + 16 * N) * applies,
         "update": 24 * N * iters_total,
         "form": 8 * N * (iters_total + solves),
-        "init": 40 * N * solves,
+        "init": 24 * N * solves,
     }
 
 

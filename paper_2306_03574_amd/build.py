@@ -30,19 +30,36 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source into libabac.so (always recompiles)."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + srcs + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libabac.so")
-    os.replace(tmp, LIB)
-    return LIB
+def build(verbose: bool = False, csrc: str = CSRC, lib: str = LIB) -> str:
+    """Compile every source into libabac.so (always recompiles).  The translation
+    units compile in parallel to objects in a temporary folder, then link."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+
+    cc = hipcc()
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    with tempfile.TemporaryDirectory(prefix="abac_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        cmds = [[cc] + flags + ["-c", os.path.join(csrc, s), "-o", o] for s, o in zip(SOURCES, objs)]
+        jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            results = list(ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds))
+        for c, res in zip(cmds, results):
+            if verbose:
+                print(" ".join(c), flush=True)
+            if res.returncode != 0:
+                sys.stderr.write(res.stdout + res.stderr)
+                raise RuntimeError(f"hipcc failed compiling {c[-3]}")
+        tmp = lib + ".tmp"
+        link = [cc, "-shared", "-fPIC", "--offload-arch=gfx950"] + objs + ["-o", tmp]
+        if verbose:
+            print(" ".join(link), flush=True)
+        res = subprocess.run(link, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking libabac.so")
+        os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

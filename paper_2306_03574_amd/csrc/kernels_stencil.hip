@@ -285,8 +285,9 @@ k_rhs(DevPlan P, const double* __restrict__ src, const double* __restrict__ psi0
   }
 }
 
-// Set-up of a solve: b = Y f into R and V_1, zero V_0 and u; ||b||^2 partials.  (The w
-// vectors are written by the flush of the resident basis before they are first read.)
+// Set-up of a solve: b = Y f into V_1, zero u; ||b||^2 partials.  (r_0 = b is read from
+// V_1 by the first residual update, v_0 is never read, and the w vectors are written
+// by the flush of the resident basis before they are first read.)
 __global__ void __launch_bounds__(kVecThreads)
 k_init(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
   const int b = blockIdx.y;
@@ -300,9 +301,7 @@ k_init(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
     const int k = (int)(e / P.m);
     const size_t i = e - (size_t)k * P.m;
     const double v = f[off + (size_t)(P.nt - 1 - k) * P.m + i];
-    P.R[off + e] = v;
-    P.V[1][off + e] = v;
-    P.V[0][off + e] = 0.0;
+    P.V[1][off + e] = v;   // v_1 = r_0 (the first update reads it as r_0)
     u[off + e] = 0.0;
     acc += v * v;
   }
@@ -322,6 +321,7 @@ k_update(DevPlan P, double* __restrict__ u) {
   const size_t off = (size_t)b * P.N;
   const double* __restrict__ Vn = P.V[(j + 1) % 3] + off;
   double* __restrict__ R = P.R + off;
+  const double* __restrict__ Rin = j == 1 ? P.V[1] + off : R;   // r_0 = v_1
   const int nblk = gridDim.x;
   const size_t per = ((size_t)P.N + nblk - 1) / nblk;
   const size_t lo = (size_t)blockIdx.x * per;
@@ -329,7 +329,7 @@ k_update(DevPlan P, double* __restrict__ u) {
   double acc = 0.0;
   if (j <= kBasis) {
     for (size_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-      const double r = r1 * R[e] + r2 * Vn[e];
+      const double r = r1 * Rin[e] + r2 * Vn[e];
       R[e] = r;
       acc += r * r;
     }
@@ -464,7 +464,7 @@ k_identity(DevPlan P, int mode, const double* __restrict__ in, double* __restric
     const int j = st->iter + 1;
     double* __restrict__ q = P.V[(j + 1) % 3] + off;
     const double* __restrict__ vj = P.V[j % 3] + off;
-    const double* __restrict__ vjm1 = P.V[(j + 2) % 3] + off;
+    const double* __restrict__ vjm1 = P.V[j == 1 ? j % 3 : (j + 2) % 3] + off;   // v_0 has weight 0 at j = 1
     double* __restrict__ z = P.Z[zslot(j + 1)] + off;
     const double cA = st->sig, cB = st->delta * st->sig, cC = st->gamma * st->sig_prev;
     for (size_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {

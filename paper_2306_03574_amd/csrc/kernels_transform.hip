@@ -140,7 +140,7 @@ k_dstx_fwd(DevPlan P, int mode, int check, const double* __restrict__ in) {
       qout = P.V[(j + 1) % 3] + off;
       src = qout;
       vj = P.V[j % 3] + off;
-      vjm1 = P.V[(j + 2) % 3] + off;
+      vjm1 = P.V[j == 1 ? j % 3 : (j + 2) % 3] + off;   // v_0 has weight 0 at j = 1
       cA = st->sig;
       cB = st->delta * st->sig;
       cC = st->gamma * st->sig_prev;
@@ -317,21 +317,47 @@ __device__ __forceinline__ void spectral_weights(SpectralWeights<T, NT>& W, int 
   }
 }
 
-// Apply the weights to the packed spectrum in LDS: Z'_k = sp Z_k + sm conj Z_{-k} and
-// the mirrored formula at -k (one thread per pair (k, nt-k)).
+// Apply the weights to the packed spectrum held in registers (v[i] = Z[j + i TPS]):
+// Z'_k = sp Z_k + sm conj Z_{-k} and Z'_{-k} = conj(sp) Z_{-k} + conj(sm) conj Z_k.
+// Thread j >= 1 owns the pairs of its low slots u < R/2 (k = j + u TPS < nt/2) with
+// the mirrored slots R-1-u of thread TPS-j, which travel through LDS at their natural
+// positions (published, updated by the owner, read back); thread 0 pairs its own
+// slots u and R-u.  The LDS region lds[e S] must be free on entry; on return other
+// threads may still be reading it.
 template <typename T, int NT>
-__device__ __forceinline__ void spectral_apply(cplx<T>* my, int S, int j, const SpectralWeights<T, NT>& W) {
+__device__ __forceinline__ void spectral_apply(cplx<T>* v, int j, cplx<T>* my, int S,
+                                               const SpectralWeights<T, NT>& W) {
   using C = cplx<T>;
-  constexpr int R = FftShape<NT>::R, TPS = NT / R;
+  constexpr int R = FftShape<NT>::R, TPS = NT / R, H = R / 2;
+  if (j != 0) {
 #pragma unroll
-  for (int u = 0; u < SpectralWeights<T, NT>::NU; ++u) {
-    const int k = j + u * TPS;
-    if (k > NT / 2 || (u == R / 2 && j != 0)) continue;
-    const int kp = (NT - k) & (NT - 1);
-    const C zk = my[k * S], zp = my[kp * S];
-    const C sp = W.sp[u], sm = W.sm[u];
-    my[k * S] = cadd(cmul(sp, zk), cmul(sm, cconj(zp)));
-    if (kp != k) my[kp * S] = cadd(cmul(cconj(sp), zp), cmul(cconj(sm), cconj(zk)));
+    for (int i = H; i < R; ++i) my[(j + i * TPS) * S] = v[i];
+  }
+  __syncthreads();
+  if (j != 0) {
+#pragma unroll
+    for (int u = 0; u < H; ++u) {
+      const int kp = NT - (j + u * TPS);
+      const C zk = v[u], zp = my[kp * S];
+      const C sp = W.sp[u], sm = W.sm[u];
+      v[u] = cadd(cmul(sp, zk), cmul(sm, cconj(zp)));
+      my[kp * S] = cadd(cmul(cconj(sp), zp), cmul(cconj(sm), cconj(zk)));
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u <= H; ++u) {
+      const int up = (R - u) & (R - 1);
+      const C zk = v[u], zp = v[up];
+      const C sp = W.sp[u], sm = W.sm[u];
+      const C a = cadd(cmul(sp, zk), cmul(sm, cconj(zp)));
+      if (up != u) v[up] = cadd(cmul(cconj(sp), zp), cmul(cconj(sm), cconj(zk)));
+      v[u] = a;
+    }
+  }
+  __syncthreads();
+  if (j != 0) {
+#pragma unroll
+    for (int i = H; i < R; ++i) v[i] = my[(j + i * TPS) * S];
   }
 }
 
@@ -382,35 +408,35 @@ k_time(DevPlan P, int check, int inv1) {
   for (int i = 0; i < R; ++i) v[i] = cscale(v[i], sc[j + i * TPS]);
   SpectralWeights<T, NT> W;
   spectral_weights<T, NT>(W, j, abk, ba, bb, (T)(0.5 / NT), inv1);
-  const int reps = inv1 ? 1 : 2;
-#pragma unroll 1
-  for (int rep = 0; rep < reps; ++rep) {
-    fft_seq<T, NT, false>(v, j, my, S, tw);
-    __syncthreads();
+  // first (or only) factor: FFT, weights, inverse FFT
+  fft_seq<T, NT, false>(v, j, my, S, tw);
+  __syncthreads();
+  spectral_apply<T, NT>(v, j, my, S, W);
+  __syncthreads();
+  fft_seq<T, NT, true>(v, j, my, S, tw);
+  if (!inv1) {
+    // D^{-1}, Y, D between the factors, y_t = a^{2t-nt+1} c_{nt-1-t}, without moving data:
+    // with g_s = y_{nt-1-s} (an elementwise scaling of c), the DFT of y at frequency k is
+    // e^{2 pi i k/nt} G_k, G the inverse-direction DFT of g.  The weights act on G as on
+    // the DFT of y (the phase at -k is the conjugate of the one at k), and the phase left
+    // on the spectrum shifts the inverse DFT by one level: out_t = w_{t+1}.
 #pragma unroll
-    for (int i = 0; i < R; ++i) my[(j + i * TPS) * S] = v[i];
-    __syncthreads();
-    spectral_apply<T, NT>(my, S, j, W);
-    __syncthreads();
-    fft_seq<T, NT, true, true>(v, j, my, S, tw);
-    if (rep == 0 && reps == 2) {
-      // D^{-1}, then Y, then D:  h_t = a^{2t-nt+1} c_{nt-1-t}
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < R; ++i) my[(j + i * TPS) * S] = v[i];
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const int t = j + i * TPS;
-        v[i] = cscale(my[(NT - 1 - t) * S], sc[t] * sci[NT - 1 - t]);
-      }
-      __syncthreads();
+    for (int i = 0; i < R; ++i) {
+      const int t = j + i * TPS;
+      v[i] = cscale(v[i], sc[NT - 1 - t] * sci[t]);
     }
+    __syncthreads();
+    fft_seq<T, NT, true>(v, j, my, S, tw);
+    __syncthreads();
+    spectral_apply<T, NT>(v, j, my, S, W);
+    __syncthreads();
+    fft_seq<T, NT, true>(v, j, my, S, tw);
   }
   if (!valid) return;
+  const int shift = inv1 ? 0 : 1;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    const int t = j + i * TPS;
+    const int t = (j + i * TPS - shift) & (NT - 1);
     g[(size_t)t * ld] = cscale(v[i], sci[t]);
   }
 }
@@ -621,7 +647,7 @@ k_dst2_fwd(DevPlan P, int mode, int check, const double* __restrict__ in) {
       qout = P.V[(j + 1) % 3] + off;
       src = qout;
       vj = P.V[j % 3] + off;
-      vjm1 = P.V[(j + 2) % 3] + off;
+      vjm1 = P.V[j == 1 ? j % 3 : (j + 2) % 3] + off;   // v_0 has weight 0 at j = 1
       cA = st->sig;
       cB = st->delta * st->sig;
       cC = st->gamma * st->sig_prev;
