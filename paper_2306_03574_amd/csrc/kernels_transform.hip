@@ -237,7 +237,10 @@ k_dsty(DevPlan P, int check) {
   if (check && P.st[b].state != ST_RUNNING) return;
   const int cpairs = P.Mx / 2;
   const int bpl = (cpairs + S - 1) / S;
-  const int t = blockIdx.x / bpl, cb = blockIdx.x % bpl;
+  // XCD-aware order: the blocks one XCD runs together read neighbouring column pairs of
+  // a level, so partial cache lines are shared in its L2
+  const int lbk = xcd_remap(blockIdx.x, gridDim.x);
+  const int t = lbk / bpl, cb = lbk % bpl;
   const int s = threadIdx.x % S, j = threadIdx.x / S;
   const int cp = cb * S + s;
   const bool valid = cp < cpairs;
@@ -379,7 +382,9 @@ k_time(DevPlan P, int check, int inv1) {
   if (check && P.st[b].state != ST_RUNNING) return;
   const int s = threadIdx.x % S, j = threadIdx.x / S;
   const int npairs = P.ms / 2;
-  const int pair = blockIdx.x * S + s;
+  // XCD-aware order: the blocks one XCD runs together read neighbouring column ranges of
+  // each time level, so partial cache lines are shared in its L2
+  const int pair = xcd_remap(blockIdx.x, gridDim.x) * S + s;
   const bool valid = pair < npairs;
   const int pc = min(pair, npairs - 1);   // clamped: the loads below are unconditional
   const int ld = npairs;
