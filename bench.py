@@ -33,7 +33,7 @@ WORKLOADS = {
     "serving_mix": dict(nx=0, ny=0, nt=0, alpha=0.0, batch=1, source="serving"),
 }
 KERNEL_CLASSES = ["stencil", "dstx_fwd", "dsty", "time", "dstx_inv", "update", "form", "residual", "init", "rhs", "fin",
-                  "gmres"]
+                  "gmres", "iter"]
 
 
 def log(msg):
@@ -61,7 +61,7 @@ def make_inputs(w):
     return np.stack(srcs), np.stack(p0s), np.stack(p1s)
 
 
-def algorithmic_bytes(w, prec, iters_total, solves):
+def algorithmic_bytes(w, prec, iters_total, solves, fused=False):
     """Algorithmic HBM bytes of every kernel class over `solves` right-hand-side solves
     that took `iters_total` MINRES iterations in total (summed over right-hand sides).
 
@@ -79,12 +79,24 @@ def algorithmic_bytes(w, prec, iters_total, solves):
       form      8 (k+1) N      (read z_1..z_k, write u) once per solve of k <= 12
                                iterations (the convergence check)
       init      24 N           (read f; write v1 = r0, u) per solve
+    With `fused` (small 1D plans, one workgroup per right-hand side runs each whole
+    iteration) the per-iteration bytes above, and the iterate formed at the check, are
+    the "iter" class; the separate classes keep their set-up pass only.
     """
     nx, ny, nt = w["nx"], w["ny"], w["nt"]
     N = nt * nx * max(ny, 1)
     NS = nt * (nx + 1) * max(ny, 1)
     s = 8 if prec == "fp64" else 4
     applies = iters_total + solves
+    if fused:
+        per_iter = 16 * N + (32 * N + s * NS) + 2 * s * NS + (s * NS + 16 * N) + 24 * N
+        return {
+            "iter": per_iter * iters_total + 8 * N * (iters_total + solves),
+            "dstx_fwd": (8 * N + s * NS) * solves,
+            "time": 2 * s * NS * solves,
+            "dstx_inv": (s * NS + 16 * N) * solves,
+            "init": 24 * N * solves,
+        }
     return {
         "stencil": 16 * N * iters_total,
         "dstx_fwd": (32 * N + s * NS) * iters_total + (8 * N + s * NS) * solves,
@@ -208,7 +220,7 @@ def run_gpu(w, prec, steps, warmup, tol, maxit, profile=True, solver="minres", r
     _, iters, relres, status = last
     u_host = u.cpu().numpy()
     return dict(elapsed=elapsed, lat=lat, iters=iters, relres=relres, status=status, iters_total=iters_total,
-                prof=prof, prof_elapsed=prof_elapsed, prof_iters=prof_iters, u=u_host)
+                prof=prof, prof_elapsed=prof_elapsed, prof_iters=prof_iters, u=u_host, tiles=plan.tiles())
 
 
 def cpu_baseline(w, tol, maxit, solver="minres", restart=15):
@@ -323,7 +335,8 @@ def main():
         abytes = algorithmic_bytes_gmres(w, prec, main_run["prof_iters"], prof["time"]["launches"],
                                          args.steps * B)
     else:
-        abytes = algorithmic_bytes(w, prec, main_run["prof_iters"], args.steps * B)
+        abytes = algorithmic_bytes(w, prec, main_run["prof_iters"], args.steps * B,
+                                   fused=main_run["tiles"].get("small", 0) > 0)
     dom = max((k for k in prof if prof[k]["launches"] > 0 and k in abytes), key=lambda k: prof[k]["ms"])
     launches = prof[dom]["launches"]
     avg_s = prof[dom]["ms"] / 1e3 / launches

@@ -78,10 +78,13 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
  * workgroup per time level applies both spatial DSTs (Section 2.3's fast sine
  * transforms) there, so the y passes over memory disappear; their tile and wg[3]
  * follow fixed rules of the shape, since they carry the <q, P^{-1} q> sums
- * (ABAC_SLAB=0 in the environment keeps the separate passes).  The other tiles are
+ * (ABAC_SLAB=0 in the environment keeps the separate passes).  wg[5] is 256 when
+ * small 1D problems (nt * nx <= 4096) run each MINRES iteration as one launch, one
+ * 256-thread workgroup per right-hand side doing every step in turn (launch latency,
+ * not memory, bounds the separate kernels there; ABAC_SMALL=0 keeps them), else 0.  The other tiles are
  * chosen by a tuner that times every legal tile on the plan's own buffers at creation
  * and caches the choice per shape (ABAC_TUNE=0 keeps 256-thread defaults;
- * ABAC_TUNE_FILE names an optional cache file).  wg must hold 5 ints. */
+ * ABAC_TUNE_FILE names an optional cache file).  wg must hold 6 ints. */
 abac_status abac_plan_tiles(abac_plan *plan, int *wg);
 
 /* Release the plan (synchronises its stream; frees library-owned memory only). */
@@ -191,7 +194,8 @@ enum {
   ABAC_K_FIN = 9,       /* per-RHS scalar steps (sums of partials)      */
   ABAC_K_FORM = 10,     /* stopping test; iterate from the resident basis */
   ABAC_K_GMRES = 11,    /* GMRES vector kernels (dots, axpys, scalings)  */
-  ABAC_K_COUNT = 12
+  ABAC_K_ITER = 12,     /* whole iteration in one workgroup per RHS (small 1D problems) */
+  ABAC_K_COUNT = 13
 };
 abac_status abac_profile_enable(abac_plan *plan, int on);
 abac_status abac_profile_read(abac_plan *plan, int kernel, double *total_ms, long long *launches);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libabac.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, EBUDGET, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7
 PREC = {"fp64": 0, "fp32": 1, "none": 2}
 KERNELS = {"stencil": 0, "dstx_fwd": 1, "dsty": 2, "time": 3, "dstx_inv": 4, "update": 5,
-           "residual": 6, "init": 7, "rhs": 8, "fin": 9, "form": 10, "gmres": 11}
+           "residual": 6, "init": 7, "rhs": 8, "fin": 9, "form": 10, "gmres": 11, "iter": 12}
 
 EXPORTED = [
     "abac_workspace_bytes", "abac_plan_create", "abac_plan_destroy", "abac_build_rhs", "abac_apply_A",
@@ -285,11 +285,14 @@ class Plan:
             float(abar)), "abac_plan_set_coefficient")
 
     def tiles(self):
-        """Workgroup sizes: dict(dstx_fwd, dsty, time, dstx_inv, slab); slab is the fused
-        x-y passes' workgroup, 0 when the plan uses separate x and y passes."""
-        wg = (ctypes.c_int * 5)()
+        """Workgroup sizes: dict(dstx_fwd, dsty, time, dstx_inv, slab, small); slab is the
+        fused x-y passes' workgroup, 0 when the plan uses separate x and y passes; small is
+        the workgroup that runs a whole iteration per right-hand side, 0 when the plan
+        launches the separate kernels."""
+        wg = (ctypes.c_int * 6)()
         _check(self._lib.abac_plan_tiles(self._h, wg), "abac_plan_tiles")
-        return {"dstx_fwd": wg[0], "dsty": wg[1], "time": wg[2], "dstx_inv": wg[3], "slab": wg[4]}
+        return {"dstx_fwd": wg[0], "dsty": wg[1], "time": wg[2], "dstx_inv": wg[3], "slab": wg[4],
+                "small": wg[5]}
 
     # -- kernel timing -----------------------------------------------------------
     def profile(self, on: bool = True):

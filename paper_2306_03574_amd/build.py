@@ -12,8 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libabac.so")
-SOURCES = ["abac_api.hip", "kernels_stencil.hip", "kernels_transform.hip", "kernels_gmres.hip", "kernels_gen.hip",
-           "server.hip"]
+SOURCES = ["abac_api.hip", "kernels_stencil.hip", "kernels_transform.hip", "kernels_small.hip", "kernels_gmres.hip",
+           "kernels_gen.hip", "server.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -250,6 +250,10 @@ abac_status enqueue_cinv(abac_plan* p, const double* r, double* z) {
 
 abac_status enqueue_iteration(abac_plan* p) {
   const DevPlan& P = p->P;
+  if (P.small) {
+    RUN(ABAC_K_ITER, launch_iter_small(P, p->prec, p->f, p->u, p->stream));
+    return ABAC_OK;
+  }
   RUN(ABAC_K_STENCIL, launch_stencil(P, STENCIL_MINRES, nullptr, nullptr, nullptr, p->stream));
   RUN(ABAC_K_FIN, launch_fin(P, FIN_DELTA, 0.0, 0, p->stream));
   abac_status s = enqueue_pinv(p, nullptr, nullptr, 2);
@@ -568,6 +572,13 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
     const char* env = std::getenv("ABAC_SLAB");
     const bool off = env && env[0] == '0';
     P.wg_s = (prec == ABAC_PREC_NONE || off) ? 0 : slab_wg(nx, ny, prec, maxlds, 8192);
+  }
+  // small 1D problems run each iteration in one workgroup per right-hand side (a rule
+  // of the shape; ABAC_SMALL=0 keeps the separate kernels)
+  {
+    const char* env = std::getenv("ABAC_SMALL");
+    const bool off = env && env[0] == '0';
+    P.small = !off && small_path_valid(nx, ny, nt, prec) ? 1 : 0;
   }
   if (prec != ABAC_PREC_NONE && (!P.wg_x || !P.wg_xi || !P.wg_y || !P.wg_t))
     return fail(ABAC_EINVAL, "transform does not fit the device LDS (" + std::to_string(maxlds) +
@@ -1012,6 +1023,7 @@ abac_status abac_plan_tiles(abac_plan* p, int* wg) {
   wg[2] = p->P.wg_t;
   wg[3] = p->P.wg_xi;
   wg[4] = p->P.wg_s;
+  wg[5] = p->P.small ? 256 : 0;
   return ABAC_OK;
 }
 

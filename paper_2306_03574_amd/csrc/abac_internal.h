@@ -120,6 +120,7 @@ struct DevPlan {
   // workgroup sizes of the transform kernels (chosen by the plan's autotuner)
   int wg_x, wg_xi, wg_y, wg_t;
   int wg_s;            // fused 2D passes (0: separate x and y passes)
+  int small;           // 1: one workgroup per right-hand side runs a whole iteration
   int st_chunk;        // forward time levels per matvec block
   int st_threads;      // columns (threads) per matvec block
   int gamma_nparts;    // partial sums of <q, P^{-1} q> per right-hand side
@@ -248,6 +249,9 @@ hipError_t launch_dstx_inv(const DevPlan& P, int prec, int mode, double* out, hi
 hipError_t launch_dst2_fwd(const DevPlan& P, int prec, int mode, int check, const double* in, hipStream_t s);
 hipError_t launch_dst2_inv(const DevPlan& P, int prec, int mode, double* out, hipStream_t s);
 int slab_wg(int nx, int ny, int prec, int maxlds, size_t margin);
+// fused small-problem iteration (1D, nt * nx <= 4096; P.small != 0)
+hipError_t launch_iter_small(const DevPlan& P, int prec, const double* f, double* u, hipStream_t s);
+bool small_path_valid(int nx, int ny, int nt, int prec);
 // transform kernel kinds (tile validity and LDS size differ per kind)
 enum TransformKind : int { TK_XFWD = 0, TK_XINV = 1, TK_Y = 2, TK_TIME = 3 };
 // dynamic LDS bytes of one workgroup (0 if the tile is not legal)

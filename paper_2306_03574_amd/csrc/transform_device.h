@@ -1,0 +1,528 @@
+// Device code of the transform passes of z = P_alpha^{-1} r (Section 2.3): per-tile
+// bodies of the first x-DST pass (with the fused Lanczos step), the y-DST pass, the time
+// pass K Y K Y (or the single K of C_alpha^{-1}) and the last x-DST pass (with the
+// partial sums of <q, p>).  Each body is one workgroup's work on one tile; the kernels
+// run one tile per workgroup, the fused small-problem iteration runs every tile of a
+// right-hand side in one workgroup.
+#pragma once
+#include "abac_internal.h"
+
+namespace abac {
+namespace {
+
+template <int L, int WG> constexpr int seqs_of() { return WG / fft_tps<L>(); }
+
+// LDS bytes of one workgroup: the interleaved sequences; the inverse x pass reuses
+// the region for its FP64 output staging; the y pass (length <= 1024) also holds its
+// twiddle table, and the time pass its twiddles, spectral coefficients (A_k, B_k) and
+// a^{+-t} scalings, each read once per block instead of once per butterfly or element.
+template <typename T, int L, int WG, int KIND>
+constexpr size_t lds_of() {
+  constexpr size_t c = sizeof(cplx<T>);
+  constexpr size_t data = (size_t)seqs_of<L, WG>() * L * c;
+  if constexpr (KIND == TK_XINV) {
+    constexpr size_t ostage = (size_t)2 * seqs_of<L, WG>() * (L / 2 + 1) * sizeof(double);
+    return data > ostage ? data : ostage;
+  } else if constexpr (KIND == TK_Y) {
+    return data + (size_t)L * c;
+  } else if constexpr (KIND == TK_TIME) {
+    return data + (size_t)3 * L * c + (size_t)2 * L * sizeof(T);
+  } else {
+    return data;
+  }
+}
+
+template <typename T, int L, int WG, int KIND>
+constexpr bool tile_ok() {
+  return WG >= fft_tps<L>() && WG % fft_tps<L>() == 0 && WG % 64 == 0 && lds_of<T, L, WG, KIND>() <= kMaxTransformLds;
+}
+
+// Copy an n-entry table into LDS (the caller places the barrier).
+template <typename V>
+__device__ __forceinline__ void stage_table(V* dst, const V* __restrict__ src, int n) {
+  for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> inv_sqrt_principal(cplx<T> mu) {
+  // 1/s(mu), s the principal square root.  With |mu| = sqrt(x^2 + y^2) and
+  // w = sqrt((|mu| + |x|)/2):  s = (w, y/(2w)) for x >= 0 and (|y|/(2w), sign(y) w)
+  // for x < 0, and 1/s = conj(s)/|mu|.  Two reciprocal square roots, no division.
+  const T x = mu.x, y = mu.y;
+  const T rr = x * x + y * y;
+  const T g = rsqrt(rr);                 // 1/|mu|
+  const T w2 = (rr * g + fabs(x)) * (T)0.5;
+  const T h = rsqrt(w2);                 // 1/w
+  const T w = w2 * h;
+  T sr, si;
+  if (x >= (T)0) {
+    sr = w;
+    si = (T)0.5 * y * h;
+  } else {
+    sr = (T)0.5 * fabs(y) * h;
+    si = copysign(w, y);
+  }
+  return cplx<T>{sr * g, -si * g};
+}
+
+// Copy a [rows][width] tile held in LDS with row stride `ld` to `rows` consecutive
+// global rows of length `width` (one contiguous range), coalesced.
+template <typename TS, typename TD>
+__device__ __forceinline__ void tile_out(TD* __restrict__ dst, const TS* src, int rows, int width, int ld) {
+  const int total = rows * width;
+  int e = threadIdx.x;
+  int r = e / width, c = e - r * width;
+  const int dr = blockDim.x / width, dc = blockDim.x - dr * width;
+  for (; e < total; e += blockDim.x) {
+    dst[e] = (TD)src[r * ld + c];
+    r += dr;
+    c += dc;
+    if (c >= width) {
+      c -= width;
+      ++r;
+    }
+  }
+}
+
+// Copy cnt <= PER * WG contiguous values of src into LDS (converted to TD): every
+// load of a thread is issued (from a clamped, in-bounds index) before any is used.
+template <int PER, int WG, typename TS, typename TD>
+__device__ __forceinline__ void stage_in(TD* dst, const TS* __restrict__ src, int cnt) {
+  TS v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) v[u] = src[min((int)threadIdx.x + u * WG, cnt - 1)];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * WG;
+    if (e < cnt) dst[e] = (TD)v[u];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// first pass: DST-I along x of every row (FP64 in, transform precision out),
+// optionally fused with the Lanczos step q = sig_j A Z_j - delta v_j - gamma_j v_{j-1}
+// ---------------------------------------------------------------------------
+// One tile (2 S rows) of right-hand side b; the caller skips stopped right-hand sides.
+template <typename T, int L, int WG>
+__device__ __forceinline__ void dstx_fwd_tile(const DevPlan& P, int mode, const double* __restrict__ in, int b,
+                                              int tile) {
+  using C = cplx<T>;
+  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_of<L, WG>(), Mx = L / 2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  T* stage = reinterpret_cast<T*>(smem);
+  const size_t off = (size_t)b * P.N;
+  const double* src = in ? in + off : nullptr;
+  double* qout = nullptr;
+  const double* vj = nullptr;
+  const double* vjm1 = nullptr;
+  double cA = 1.0, cB = 0.0, cC = 0.0;
+  if (mode == FWD_LANCZOS) {
+    const MinresState* st = P.st + b;
+    const int j = st->iter + 1;
+    qout = P.V[(j + 1) % 3] + off;
+    src = qout;
+    vj = P.V[j % 3] + off;
+    vjm1 = P.V[j == 1 ? j % 3 : (j + 2) % 3] + off;   // v_0 has weight 0 at j = 1
+    cA = st->sig;
+    cB = st->delta * st->sig;
+    cC = st->gamma * st->sig_prev;
+  }
+  const int nx = P.nx;
+  const int rows = P.nt * P.ny1;
+  const int row0 = tile * 2 * S;
+  const int nrows = min(2 * S, rows - row0);
+  const size_t base = (size_t)row0 * nx;
+  const int cnt = nrows * nx;
+  // cnt <= 2 S nx < WG * R: each thread stages at most R values, in batches whose
+  // loads (clamped to the tile, so unconditional) are all issued before they are used
+  constexpr int BATCH = 4;
+  if (mode == FWD_LANCZOS) {
+#pragma unroll
+    for (int u0 = 0; u0 < R; u0 += BATCH) {
+      double a[BATCH], bv[BATCH], cv[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const size_t e = base + min((int)threadIdx.x + (u0 + u) * WG, cnt - 1);
+        a[u] = src[e];
+        bv[u] = vj[e];
+        cv[u] = vjm1[e];
+      }
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int e = threadIdx.x + (u0 + u) * WG;
+        if (e < cnt) {
+          const double q = cA * a[u] - cB * bv[u] - cC * cv[u];
+          qout[base + e] = q;
+          stage[e] = (T)q;
+        }
+      }
+    }
+  } else {
+    stage_in<R, WG>(stage, src + base, cnt);
+  }
+  __syncthreads();
+  const int s = threadIdx.x % S, j = threadIdx.x / S;
+  const int ra = 2 * s, rb = 2 * s + 1;
+  const bool va = ra < nrows, vb = rb < nrows;
+  C v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int t = j + i * TPS;
+    T a = 0, c = 0;
+    if (t > 0 && t < Mx) {
+      if (va) a = stage[ra * nx + t - 1];
+      if (vb) c = stage[rb * nx + t - 1];
+    } else if (t > Mx) {
+      const int idx = 2 * Mx - t - 1;
+      if (va) a = -stage[ra * nx + idx];
+      if (vb) c = -stage[rb * nx + idx];
+    }
+    v[i] = C{a, c};
+  }
+  __syncthreads();
+  fft_seq<T, L, false>(v, j, lds + s, S, reinterpret_cast<const C*>(P.twx));
+  const T scl = (T)(1.0 / sqrt((double)L));
+  // stage the transformed rows ([2S][Mx+1] padded) and write them out contiguously
+  __syncthreads();
+  constexpr int LDO = Mx + 1;
+#pragma unroll
+  for (int i = 0; i <= R / 2; ++i) {
+    const int k = j + i * TPS;
+    if (k == 0 || k > Mx) continue;
+    if (k == Mx) {
+      stage[ra * LDO + Mx - 1] = 0;
+      stage[rb * LDO + Mx - 1] = 0;
+    } else {
+      stage[ra * LDO + k - 1] = -v[i].y * scl;
+      stage[rb * LDO + k - 1] = v[i].x * scl;
+    }
+  }
+  __syncthreads();
+  T* out = reinterpret_cast<T*>(P.scratch) + (size_t)b * P.NS + (size_t)row0 * Mx;
+  tile_out<T, T>(out, stage, nrows, Mx, LDO);
+}
+
+// ---------------------------------------------------------------------------
+// y pass (2D): DST-I along y of every column, in place on the scratch; two adjacent
+// columns form one complex sequence.
+// ---------------------------------------------------------------------------
+// One block of right-hand side b (logical block index lbk).
+template <typename T, int L, int WG>
+__device__ __forceinline__ void dsty_tile(const DevPlan& P, int b, int lbk) {
+  using C = cplx<T>;
+  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_of<L, WG>(), My = L / 2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* tws = reinterpret_cast<C*>(smem);
+  C* lds = tws + L;
+  const int cpairs = P.Mx / 2;
+  const int bpl = (cpairs + S - 1) / S;
+  const int t = lbk / bpl, cb = lbk % bpl;
+  const int s = threadIdx.x % S, j = threadIdx.x / S;
+  const int cp = cb * S + s;
+  const bool valid = cp < cpairs;
+  const int ld = P.Mx / 2;
+  C* col = reinterpret_cast<C*>(reinterpret_cast<T*>(P.scratch) + (size_t)b * P.NS + (size_t)t * P.ms) +
+           min(cp, cpairs - 1);   // clamped: the loads below are unconditional
+  C v[R];
+  // odd extension of the column: element tt is x[tt-1] for 0 < tt < My, -x[2 My - tt - 1]
+  // for tt > My, 0 at tt = 0 and tt = My
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int tt = j + i * TPS;
+    const int src = tt < My ? max(tt - 1, 0) : min(2 * My - tt - 1, My - 2);
+    v[i] = col[(size_t)src * ld];
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int tt = j + i * TPS;
+    const bool zero = !valid || tt == 0 || tt == My;
+    v[i] = zero ? C{0, 0} : (tt < My ? v[i] : C{-v[i].x, -v[i].y});
+  }
+  stage_table(tws, reinterpret_cast<const C*>(P.twy), L);
+  __syncthreads();
+  fft_seq<T, L, false>(v, j, lds + s, S, tws);
+  const T scl = (T)(1.0 / sqrt((double)L));
+  if (!valid) return;
+#pragma unroll
+  for (int i = 0; i <= R / 2; ++i) {
+    const int k = j + i * TPS;
+    if (k == 0 || k >= My) continue;
+    col[(size_t)(k - 1) * ld] = C{-v[i].y * scl, v[i].x * scl};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// time pass: per spatial mode pair, out = K Y K Y g, in place on the scratch.
+// ---------------------------------------------------------------------------
+
+// Spectral weights of two real modes packed as one complex sequence z = g_a + i g_b:
+// with Z = F z, the spectra of the two modes are (Z_k + conj Z_{-k})/2 and
+// (Z_k - conj Z_{-k})/(2i); weighting them by Ma_k, Mb_k and repacking gives
+//   Z'_k = ((Ma + Mb) Z_k + (Ma - Mb) conj Z_{-k}) / 2.
+// mu is Hermitian in k (mu_{-k} = conj mu_k), so one thread handles the pair
+// (k, nt-k) with a single evaluation of Ma_k, Mb_k.  Input and output in LDS, natural
+// order; `scale` folds in the 1/nt of the inverse DFT.  The weights are mu^{-1/2}
+// (ABAC factor) or, with inv1, mu^{-1} (the block alpha-circulant C_alpha^{-1}).
+// 1/mu (the weights of C_alpha^{-1} itself)
+template <typename T>
+__device__ __forceinline__ cplx<T> inv_complex(cplx<T> mu) {
+  const T g = (T)1 / (mu.x * mu.x + mu.y * mu.y);
+  return cplx<T>{mu.x * g, -mu.y * g};
+}
+
+template <typename T, int NT>
+struct SpectralWeights {
+  static constexpr int NU = FftShape<NT>::R / 2 + 1;   // frequency slots of one thread
+  cplx<T> sp[NU], sm[NU];
+};
+
+// The weights (Ma + Mb)/2 and (Ma - Mb)/2 (times `scale`) of the frequencies
+// k = j + u TPS <= NT/2 this thread handles; they depend on the mode pair only, so both
+// passes of K Y K Y use the same ones.
+template <typename T, int NT>
+__device__ __forceinline__ void spectral_weights(SpectralWeights<T, NT>& W, int j, const cplx<T>* abk, T ba, T bb,
+                                                 T scale, int inv1) {
+  using C = cplx<T>;
+  constexpr int R = FftShape<NT>::R, TPS = NT / R;
+#pragma unroll
+  for (int u = 0; u < SpectralWeights<T, NT>::NU; ++u) {
+    const int k = min(j + u * TPS, NT / 2);   // out-of-range slots are never applied
+    const C A = abk[2 * k], Bk = abk[2 * k + 1];
+    const C mua = C{A.x + ba * Bk.x, A.y + ba * Bk.y}, mub = C{A.x + bb * Bk.x, A.y + bb * Bk.y};
+    const C Ma = inv1 ? inv_complex<T>(mua) : inv_sqrt_principal<T>(mua);
+    const C Mb = inv1 ? inv_complex<T>(mub) : inv_sqrt_principal<T>(mub);
+    W.sp[u] = cscale(cadd(Ma, Mb), scale);
+    W.sm[u] = cscale(csub(Ma, Mb), scale);
+  }
+}
+
+// Apply the weights to the packed spectrum held in registers (v[i] = Z[j + i TPS]):
+// Z'_k = sp Z_k + sm conj Z_{-k} and Z'_{-k} = conj(sp) Z_{-k} + conj(sm) conj Z_k.
+// Thread j >= 1 owns the pairs of its low slots u < R/2 (k = j + u TPS < nt/2) with
+// the mirrored slots R-1-u of thread TPS-j, which travel through LDS at their natural
+// positions (published, updated by the owner, read back); thread 0 pairs its own
+// slots u and R-u.  The LDS region lds[e S] must be free on entry; on return other
+// threads may still be reading it.
+template <typename T, int NT>
+__device__ __forceinline__ void spectral_apply(cplx<T>* v, int j, cplx<T>* my, int S,
+                                               const SpectralWeights<T, NT>& W) {
+  using C = cplx<T>;
+  constexpr int R = FftShape<NT>::R, TPS = NT / R, H = R / 2;
+  if (j != 0) {
+#pragma unroll
+    for (int i = H; i < R; ++i) my[(j + i * TPS) * S] = v[i];
+  }
+  __syncthreads();
+  if (j != 0) {
+#pragma unroll
+    for (int u = 0; u < H; ++u) {
+      const int kp = NT - (j + u * TPS);
+      const C zk = v[u], zp = my[kp * S];
+      const C sp = W.sp[u], sm = W.sm[u];
+      v[u] = cadd(cmul(sp, zk), cmul(sm, cconj(zp)));
+      my[kp * S] = cadd(cmul(cconj(sp), zp), cmul(cconj(sm), cconj(zk)));
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u <= H; ++u) {
+      const int up = (R - u) & (R - 1);
+      const C zk = v[u], zp = v[up];
+      const C sp = W.sp[u], sm = W.sm[u];
+      const C a = cadd(cmul(sp, zk), cmul(sm, cconj(zp)));
+      if (up != u) v[up] = cadd(cmul(cconj(sp), zp), cmul(cconj(sm), cconj(zk)));
+      v[u] = a;
+    }
+  }
+  __syncthreads();
+  if (j != 0) {
+#pragma unroll
+    for (int i = H; i < R; ++i) v[i] = my[(j + i * TPS) * S];
+  }
+}
+
+// inv1 = 0: out = K Y K Y g with mu^{-1/2} (the ABAC P^{-1}); inv1 = 1: out = K g with
+// mu^{-1} and no time reversal (C_alpha^{-1} = S K S of eqs. (1.5)-(1.7)).
+// One block (S mode pairs, logical block index lbk) of right-hand side b.
+template <typename T, int NT, int WG>
+__device__ __forceinline__ void time_tile(const DevPlan& P, int inv1, int b, int lbk) {
+  using C = cplx<T>;
+  constexpr int R = FftShape<NT>::R, TPS = NT / R, S = seqs_of<NT, WG>();
+  extern __shared__ __align__(16) unsigned char smem[];
+  // LDS: twiddles [NT], (A_k, B_k) [2 NT], a^t [NT], a^-t [NT], then the sequences
+  C* tws = reinterpret_cast<C*>(smem);
+  C* abk = tws + NT;
+  T* sc = reinterpret_cast<T*>(abk + 2 * NT);
+  T* sci = sc + NT;
+  C* lds = reinterpret_cast<C*>(sci + NT);
+  const int s = threadIdx.x % S, j = threadIdx.x / S;
+  const int npairs = P.ms / 2;
+  const int pair = lbk * S + s;
+  const bool valid = pair < npairs;
+  const int pc = min(pair, npairs - 1);   // clamped: the loads below are unconditional
+  const int ld = npairs;
+  C* g = reinterpret_cast<C*>(reinterpret_cast<T*>(P.scratch) + (size_t)b * P.NS) + pair;
+  const C* gin = reinterpret_cast<const C*>(reinterpret_cast<const T*>(P.scratch) + (size_t)b * P.NS) + pc;
+  const T* __restrict__ beta = reinterpret_cast<const T*>(P.beta);
+  const T ba = valid ? beta[2 * pc] : (T)1;
+  const T bb = valid ? beta[2 * pc + 1] : (T)1;
+  C* my = lds + s;
+  C v[R];
+  // Y (ABAC only): e_t = g_{nt-1-t}; the D scaling follows once the table is in LDS
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int t = j + i * TPS;
+    v[i] = gin[(size_t)(inv1 ? t : NT - 1 - t) * ld];
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = valid ? v[i] : C{0, 0};
+  stage_table(tws, reinterpret_cast<const C*>(P.twt), NT);
+  stage_table(abk, reinterpret_cast<const C*>(P.abk), 2 * NT);
+  stage_table(sc, reinterpret_cast<const T*>(P.sc), NT);
+  stage_table(sci, reinterpret_cast<const T*>(P.sci), NT);
+  __syncthreads();
+  const C* tw = tws;
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = cscale(v[i], sc[j + i * TPS]);
+  SpectralWeights<T, NT> W;
+  spectral_weights<T, NT>(W, j, abk, ba, bb, (T)(0.5 / NT), inv1);
+  // first (or only) factor: FFT, weights, inverse FFT
+  fft_seq<T, NT, false>(v, j, my, S, tw);
+  __syncthreads();
+  spectral_apply<T, NT>(v, j, my, S, W);
+  __syncthreads();
+  fft_seq<T, NT, true>(v, j, my, S, tw);
+  if (!inv1) {
+    // D^{-1}, Y, D between the factors, y_t = a^{2t-nt+1} c_{nt-1-t}, without moving data:
+    // with g_s = y_{nt-1-s} (an elementwise scaling of c), the DFT of y at frequency k is
+    // e^{2 pi i k/nt} G_k, G the inverse-direction DFT of g.  The weights act on G as on
+    // the DFT of y (the phase at -k is the conjugate of the one at k), and the phase left
+    // on the spectrum shifts the inverse DFT by one level: out_t = w_{t+1}.
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int t = j + i * TPS;
+      v[i] = cscale(v[i], sc[NT - 1 - t] * sci[t]);
+    }
+    __syncthreads();
+    fft_seq<T, NT, true>(v, j, my, S, tw);
+    __syncthreads();
+    spectral_apply<T, NT>(v, j, my, S, W);
+    __syncthreads();
+    fft_seq<T, NT, true>(v, j, my, S, tw);
+  }
+  if (!valid) return;
+  const int shift = inv1 ? 0 : 1;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int t = (j + i * TPS - shift) & (NT - 1);
+    g[(size_t)t * ld] = cscale(v[i], sci[t]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// last pass: inverse DST-I along x (transform precision in, FP64 out), optionally
+// fused with the partial sums of <q, p>.
+// ---------------------------------------------------------------------------
+// One tile (2 S rows) of right-hand side b; returns this thread's part of <q, p> (0 in
+// INV_PLAIN).  The caller skips stopped right-hand sides.
+template <typename T, int L, int WG>
+__device__ __forceinline__ double dstx_inv_tile(const DevPlan& P, int mode, double* __restrict__ outp, int b,
+                                                int tile) {
+  using C = cplx<T>;
+  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_of<L, WG>(), Mx = L / 2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  T* stage = reinterpret_cast<T*>(smem);
+  double* ostage = reinterpret_cast<double*>(smem);
+  const size_t off = (size_t)b * P.N;
+  double* out = outp ? outp + off : nullptr;
+  const double* q = nullptr;
+  const MinresState* st = P.st + b;
+  if (mode != INV_PLAIN) {
+    if (mode == INV_GAMMA_INIT) {
+      out = P.Z[zslot(1)] + off;
+      q = P.V[1] + off;
+    } else {
+      const int jj = st->iter + 1;
+      out = P.Z[zslot(jj + 1)] + off;
+      q = P.V[(jj + 1) % 3] + off;
+    }
+  }
+  const int nx = P.nx;
+  const int rows = P.nt * P.ny1;
+  const int row0 = tile * 2 * S;
+  const int nrows = min(2 * S, rows - row0);
+  const T* scr = reinterpret_cast<const T*>(P.scratch) + (size_t)b * P.NS + (size_t)row0 * Mx;
+  const int cnt = nrows * Mx;   // <= 2 S Mx = WG * R
+  stage_in<R, WG>(stage, scr, cnt);
+  __syncthreads();
+  const int s = threadIdx.x % S, j = threadIdx.x / S;
+  const int ra = 2 * s, rb = 2 * s + 1;
+  const bool va = ra < nrows, vb = rb < nrows;
+  C v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int t = j + i * TPS;
+    T a = 0, c = 0;
+    if (t > 0 && t < Mx) {
+      if (va) a = stage[ra * Mx + t - 1];
+      if (vb) c = stage[rb * Mx + t - 1];
+    } else if (t > Mx) {
+      const int idx = 2 * Mx - t - 1;
+      if (va) a = -stage[ra * Mx + idx];
+      if (vb) c = -stage[rb * Mx + idx];
+    }
+    v[i] = C{a, c};
+  }
+  __syncthreads();
+  fft_seq<T, L, false>(v, j, lds + s, S, reinterpret_cast<const C*>(P.twx));
+  const double scl = 1.0 / sqrt((double)L);
+  // stage the FP64 rows ([2S][nx+2] padded: odd stride in 8-byte words) and write
+  // them out contiguously; with q, accumulate <q, p> in a fixed order for a fixed tile
+  __syncthreads();
+  const int ldo = nx + 2;
+#pragma unroll
+  for (int i = 0; i <= R / 2; ++i) {
+    const int k = j + i * TPS;
+    if (k == 0 || k >= Mx) continue;
+    ostage[ra * ldo + k - 1] = -(double)v[i].y * scl;
+    ostage[rb * ldo + k - 1] = (double)v[i].x * scl;
+  }
+  __syncthreads();
+  double* o = out + (size_t)row0 * nx;
+  const int total = nrows * nx;   // < WG * R
+  double acc = 0.0;
+  {
+    const double* qq = q ? q + (size_t)row0 * nx : nullptr;
+    int r = (int)threadIdx.x / nx, c = (int)threadIdx.x - r * nx;
+    const int dr = WG / nx, dc = WG - dr * nx;
+    constexpr int BATCH = 8;
+#pragma unroll
+    for (int u0 = 0; u0 < R; u0 += BATCH) {
+      double qv[BATCH];
+      if (qq) {
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) qv[u] = qq[min((int)threadIdx.x + (u0 + u) * WG, total - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int e = threadIdx.x + (u0 + u) * WG;
+        if (e < total) {
+          const double val = ostage[r * ldo + c];
+          o[e] = val;
+          if (qq) acc += val * qv[u];
+        }
+        r += dr;
+        c += dc;
+        if (c >= nx) {
+          c -= nx;
+          ++r;
+        }
+      }
+    }
+  }
+  return acc;
+}
+
+}  // namespace
+}  // namespace abac

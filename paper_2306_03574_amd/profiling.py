@@ -30,7 +30,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CLASS_OF = OrderedDict([
     ("k_stencil", "stencil"), ("k_dstx_fwd", "dstx_fwd"), ("k_dsty", "dsty"), ("k_time", "time"),
     ("k_dstx_inv", "dstx_inv"), ("k_update", "update"), ("k_form", "form"), ("k_init", "init"),
-    ("k_rhs", "rhs"), ("k_fin", "fin"), ("k_identity", "identity"),
+    ("k_rhs", "rhs"), ("k_fin", "fin"), ("k_identity", "identity"), ("k_iter_small", "iter"),
 ])
 
 

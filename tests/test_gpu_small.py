@@ -1,0 +1,126 @@
+"""GPU: the fused small-problem iteration (one workgroup per right-hand side runs a whole
+MINRES iteration, 1D plans with nt * nx <= 4096) against the separate kernels
+(ABAC_SMALL=0 at plan creation) and against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.discretization import Grid, L_matrix
+from oracle import allatonce as aao
+from oracle import preconditioner as pc
+from oracle import minres as mr
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _plan(nx, nt, alpha=1e-3, prec="fp64", batch=1, small=True, monkeypatch=None):
+    from paper_2306_03574_amd import Plan
+    print(f"[case] nx={nx} nt={nt} alpha={alpha} prec={prec} batch={batch} small={small}", flush=True)
+    monkeypatch.setenv("ABAC_SMALL", "1" if small else "0")
+    return Plan(nx, 0, nt, T=1.0, alpha=alpha, prec=prec, batch=batch, device=DEV)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("nx,nt,want", [(63, 64, True), (7, 8, True), (15, 256, True), (127, 64, False),
+                                        (1023, 8, False), (63, 128, False)])
+def test_which_plans_fuse_the_iteration(nx, nt, want, monkeypatch):
+    assert (_plan(nx, nt, monkeypatch=monkeypatch).tiles()["small"] > 0) == want
+    assert _plan(nx, nt, small=False, monkeypatch=monkeypatch).tiles()["small"] == 0
+
+
+CASES = [(7, 8, 1e-2, "fp64"), (15, 16, 1e-3, "fp64"), (63, 64, 1e-1, "fp64"), (63, 64, 1e-3, "fp32"),
+         (15, 256, 1e-3, "fp64"), (7, 256, 1e-2, "fp32"), (31, 128, 1e-3, "fp64")]
+
+
+@pytest.mark.parametrize("nx,nt,alpha,prec", CASES)
+def test_fused_iteration_matches_separate_kernels(nx, nt, alpha, prec, monkeypatch):
+    """Same iteration count and status; iterates equal to rounding (the two routes sum
+    their partials in different orders; with FP32 transforms that rounding reaches the
+    iterate through a preconditioner that is itself only accurate to eps32 / alpha, so
+    there both iterates are held to what the stopping rule fixes)."""
+    src, psi0, psi1 = synth.random_source(nx, 0, nt, seed=51)
+    g = Grid(nx, 0, nt)
+    f = aao.build_rhs(g, src, psi0, psi1)
+    res = []
+    for small in (True, False):
+        p = _plan(nx, nt, alpha=alpha, prec=prec, small=small, monkeypatch=monkeypatch)
+        assert (p.tiles()["small"] > 0) == small
+        u, iters, relres, status = p.solve(_dev(f[None]), tol=1e-8, maxit=300)
+        res.append((_host(u)[0], iters[0], relres[0], status[0]))
+    (u1, i1, r1, s1), (u2, i2, r2, s2) = res
+    assert s1 == s2 == 0 and i1 == i2 and r1 <= 1e-8 and r2 <= 1e-8
+    assert _rel(u1, u2) < (1e-10 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("k", [1, 3, 12, 13, 15])
+def test_fused_fixed_iterates_match_oracle(k, monkeypatch):
+    """x_k after exactly k iterations (across the resident-basis flush at 12) equals the
+    oracle's."""
+    nx, nt, alpha = 63, 64, 1e-1
+    g = Grid(nx, 0, nt)
+    src, psi0, psi1 = synth.random_source(nx, 0, nt, seed=52)
+    f = aao.build_rhs(g, src, psi0, psi1)
+    L = L_matrix(g)
+    ref = mr.minres(lambda v: aao.apply_A(g, v, L), lambda y: pc.apply_Pinv(g, alpha, y), aao.reverse_time(f),
+                    fixed_iters=k)
+    p = _plan(nx, nt, alpha=alpha, monkeypatch=monkeypatch)
+    assert p.tiles()["small"] > 0
+    u, iters, relres, status = p.solve(_dev(f[None]), tol=1e-30, maxit=k)
+    assert iters == [k] and status == [-4]
+    assert _rel(_host(u)[0], ref.x) < 1e-10
+    assert abs(relres[0] - ref.relres) < 1e-8 * max(ref.relres, 1e-3)
+
+
+def test_fused_batch_equals_solo_and_edge_cases(monkeypatch):
+    """Each right-hand side of a batch equals its solo solve bit for bit; a zero
+    right-hand side stops at once with u = 0, and maxit stops with ENOTCONV."""
+    nx, nt, alpha = 63, 64, 1e-3
+    g = Grid(nx, 0, nt)
+    fs = []
+    for seed in (61, 62, 63):
+        src, psi0, psi1 = synth.random_source(nx, 0, nt, seed=seed)
+        fs.append(aao.build_rhs(g, src, psi0, psi1))
+    fs[1] = np.zeros_like(fs[1])
+    pb = _plan(nx, nt, alpha=alpha, batch=3, monkeypatch=monkeypatch)
+    ub, itb, rrb, stb = pb.solve(_dev(np.stack(fs)), tol=1e-8, maxit=200)
+    ubh = _host(ub)
+    assert stb == [0, 0, 0] and itb[1] == 0 and not ubh[1].any()
+    ps = _plan(nx, nt, alpha=alpha, monkeypatch=monkeypatch)
+    for i in (0, 2):
+        us, its, rrs, sts = ps.solve(_dev(fs[i][None]), tol=1e-8, maxit=200)
+        assert its[0] == itb[i] and np.array_equal(_host(us)[0], ubh[i])
+    um, itm, rrm, stm = ps.solve(_dev(fs[0][None]), tol=1e-14, maxit=3)
+    assert itm == [3] and stm == [-4]
+
+
+def test_fused_variable_coefficient(monkeypatch):
+    """Variable-coefficient matvec inside the fused iteration: same result as the
+    separate kernels."""
+    nx, nt, alpha = 63, 64, 1e-2
+    rng = np.random.default_rng(71)
+    a_xh = 1.0 + 0.1 * rng.random(nx + 1)
+    src, psi0, psi1 = synth.random_source(nx, 0, nt, seed=72)
+    res = []
+    for small in (True, False):
+        p = _plan(nx, nt, alpha=alpha, small=small, monkeypatch=monkeypatch)
+        p.set_coefficient(a_xh, None, abar=float(np.mean(0.5 * (a_xh[1:] + a_xh[:-1]))))
+        f = p.build_rhs(_dev(src[None]), _dev(psi0[None]), _dev(psi1[None]))
+        u, iters, relres, status = p.solve(f, tol=1e-8, maxit=300)
+        res.append((_host(u)[0], iters[0], status[0]))
+    assert res[0][2] == res[1][2] == 0 and res[0][1] == res[1][1]
+    assert _rel(res[0][0], res[1][0]) < 1e-10
