@@ -884,6 +884,10 @@ abac_status abac_minres_begin(abac_plan* p, const double* f, double* u, double t
   p->u = u;
   p->active = true;
   p->ring_posted = 0;
+  if (p->P.small) {
+    RUN(ABAC_K_INIT, launch_setup_small(p->P, p->prec, f, u, tol, maxit, p->stream));   // ends with the snapshot
+    return record_snapshot_event(p);
+  }
   RUN(ABAC_K_INIT, launch_init(p->P, f, u, tol, maxit, p->stream));
   abac_status s = enqueue_pinv(p, nullptr, nullptr, 1);   // ends with the set-up snapshot
   if (s != ABAC_OK) return s;

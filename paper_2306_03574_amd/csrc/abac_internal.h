@@ -251,6 +251,8 @@ hipError_t launch_dst2_inv(const DevPlan& P, int prec, int mode, double* out, hi
 int slab_wg(int nx, int ny, int prec, int maxlds, size_t margin);
 // fused small-problem iteration (1D, nt * nx <= 4096; P.small != 0)
 hipError_t launch_iter_small(const DevPlan& P, int prec, const double* f, double* u, hipStream_t s);
+hipError_t launch_setup_small(const DevPlan& P, int prec, const double* f, double* u, double tol, int maxit,
+                              hipStream_t s);
 bool small_path_valid(int nx, int ny, int nt, int prec);
 // transform kernel kinds (tile validity and LDS size differ per kind)
 enum TransformKind : int { TK_XFWD = 0, TK_XINV = 1, TK_Y = 2, TK_TIME = 3 };

@@ -1,4 +1,4 @@
-// Fused MINRES iteration for small 1D problems (N = nt * nx <= 4096 unknowns).
+// Fused MINRES set-up and iteration for small 1D problems (N = nt * nx <= 4096 unknowns).
 //
 // At these sizes an iteration of the separate kernels (matvec, scalar step, three
 // transform passes, scalar step, update, scalar step, iterate, residual, scalar step)
@@ -131,13 +131,64 @@ k_iter_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
   }
 }
 
+// Set-up of a solve of right-hand side blockIdx.x in one workgroup: b = Y f into v_1,
+// u = 0, ||b||^2, then z_1 = P^{-1} b and gamma_1 (the separate kernels' set-up and
+// first preconditioner apply, in the same order and under the same conditions).
 template <typename T, int L, int NT>
-hipError_t launch_small_t(const DevPlan& P, const double* f, double* u, hipStream_t s) {
+__global__ void __launch_bounds__(kSmallWG)
+k_setup_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u, double tol, int maxit) {
+  constexpr int WG = kSmallWG;
+  const int b = blockIdx.x;
+  const size_t off = (size_t)b * P.N;
+  MinresState* st = P.st + b;
+  const int tid = threadIdx.x;
+  {
+    double acc = 0.0;
+    for (int e = tid; e < P.N; e += WG) {
+      const int k = e / P.m;
+      const double v = f[off + (size_t)(P.nt - 1 - k) * P.m + (e - k * P.m)];
+      P.V[1][off + e] = v;
+      u[off + e] = 0.0;
+      acc += v * v;
+    }
+    const double tot = block_sum(acc);
+    if (fin_begin(P, b, FIN_BNORM) && tid == 0) fin_scalar(P, b, FIN_BNORM, tot, tol, maxit);
+    __syncthreads();
+  }
+  double tot = 0.0;
+  if (st->state == ST_RUNNING) {
+    constexpr int SX = seqs_of<L, WG>(), ST = seqs_of<NT, WG>();
+    const int xtiles = (P.nt + 2 * SX - 1) / (2 * SX);
+    const int ttiles = (P.ms / 2 + ST - 1) / ST;
+    for (int t = 0; t < xtiles; ++t) {
+      dstx_fwd_tile<T, L, WG>(P, FWD_PLAIN, P.V[1], b, t);
+      __syncthreads();
+    }
+    for (int t = 0; t < ttiles; ++t) {
+      time_tile<T, NT, WG>(P, 0, b, t);
+      __syncthreads();
+    }
+    double acc = 0.0;
+    for (int t = 0; t < xtiles; ++t) {
+      acc += dstx_inv_tile<T, L, WG>(P, INV_GAMMA_INIT, nullptr, b, t);
+      __syncthreads();
+    }
+    tot = block_sum(acc);
+  }
+  if (fin_begin(P, b, FIN_GAMMA_INIT) && tid == 0) fin_scalar(P, b, FIN_GAMMA_INIT, tot, 0.0, 0);
+}
+
+template <typename T, int L, int NT>
+hipError_t launch_small_t(const DevPlan& P, const double* f, double* u, hipStream_t s, bool setup, double tol,
+                          int maxit) {
   if constexpr (!small_ok<T, L, NT>()) {
     return hipErrorInvalidValue;
   } else {
     constexpr size_t lds = small_lds<T, L, NT>();
-    hipLaunchKernelGGL((k_iter_small<T, L, NT>), dim3(P.B), dim3(kSmallWG), lds, s, P, f, u);
+    if (setup)
+      hipLaunchKernelGGL((k_setup_small<T, L, NT>), dim3(P.B), dim3(kSmallWG), lds, s, P, f, u, tol, maxit);
+    else
+      hipLaunchKernelGGL((k_iter_small<T, L, NT>), dim3(P.B), dim3(kSmallWG), lds, s, P, f, u);
     return hipGetLastError();
   }
 }
@@ -154,8 +205,9 @@ hipError_t launch_small_t(const DevPlan& P, const double* f, double* u, hipStrea
   }
 
 template <typename T>
-hipError_t small_dispatch(const DevPlan& P, const double* f, double* u, hipStream_t s) {
-#define CALL(LL, NN) launch_small_t<T, LL, NN>(P, f, u, s)
+hipError_t small_dispatch(const DevPlan& P, const double* f, double* u, hipStream_t s, bool setup, double tol,
+                          int maxit) {
+#define CALL(LL, NN) launch_small_t<T, LL, NN>(P, f, u, s, setup, tol, maxit)
   switch (2 * P.Mx) {
     case 16: ABAC_SMALL_NT(16, CALL)
     case 32: ABAC_SMALL_NT(32, CALL)
@@ -191,7 +243,13 @@ bool small_valid_t(int L, int nt) {
 }  // namespace
 
 hipError_t launch_iter_small(const DevPlan& P, int prec, const double* f, double* u, hipStream_t s) {
-  return prec ? small_dispatch<float>(P, f, u, s) : small_dispatch<double>(P, f, u, s);
+  return prec ? small_dispatch<float>(P, f, u, s, false, 0.0, 0) : small_dispatch<double>(P, f, u, s, false, 0.0, 0);
+}
+
+hipError_t launch_setup_small(const DevPlan& P, int prec, const double* f, double* u, double tol, int maxit,
+                              hipStream_t s) {
+  return prec ? small_dispatch<float>(P, f, u, s, true, tol, maxit)
+              : small_dispatch<double>(P, f, u, s, true, tol, maxit);
 }
 
 bool small_path_valid(int nx, int ny, int nt, int prec) {
