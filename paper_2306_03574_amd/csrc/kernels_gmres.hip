@@ -5,7 +5,11 @@
 //
 // One Arnoldi step j (all right-hand sides in lockstep, grid.y = RHS):
 //   z = C^{-1} v_j;  w = T z;
-//   classical Gram-Schmidt twice: h = V^T w, w -= V h (two passes, fixed-order sums);
+//   classical Gram-Schmidt: h1 = V^T w, w -= V h1; a second pass h2 = V^T w, w -= V h2
+//   only when the first removed more than half of ||w||^2 (the Daniel-Gragg-Kaufman-
+//   Stewart test with eta = 1/sqrt(2), ||w - V h1||^2 = ||w||^2 - ||h1||^2 in exact
+//   arithmetic); the dots of the second pass ride along with the update of the first;
+//   fixed-order sums;
 //   H(:, j) = h1 + h2, H(j+1, j) = ||w||;  Givens rotations;  v_{j+1} = w / ||w||.
 // When the rotated residual meets tol, the cycle ends or maxit is reached, the iterate
 // u = X0 + C^{-1}(V y) is formed (X0: the iterate at the start of the cycle) and the
@@ -52,17 +56,17 @@ k_ginit(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
   if (threadIdx.x == 0) part_slot(P, PART_RNORM, b)[blockIdx.x] = bs;
 }
 
-// partial sums of <v_l, w>, l = 0..J
-template <int J>
+// partial sums of <v_l, w>, l = 0..J, and with NORM also of <w, w> (slot J+1)
+template <int J, bool NORM>
 __device__ __forceinline__ void gdots_body(const DevPlan& P, int b, const double* __restrict__ w) {
   const size_t off = (size_t)b * P.N;
   const double* vs[J + 1];
 #pragma unroll
   for (int l = 0; l <= J; ++l) vs[l] = gslot(P, l) + off;
   const double* ww = w + off;
-  double acc[J + 1];
+  double acc[J + 2];
 #pragma unroll
-  for (int l = 0; l <= J; ++l) acc[l] = 0.0;
+  for (int l = 0; l <= J + 1; ++l) acc[l] = 0.0;
   size_t lo, hi;
   elem_range(P, &lo, &hi);
   for (size_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
@@ -72,15 +76,18 @@ __device__ __forceinline__ void gdots_body(const DevPlan& P, int b, const double
     for (int l = 0; l <= J; ++l) v[l] = vs[l][e];
 #pragma unroll
     for (int l = 0; l <= J; ++l) acc[l] += v[l] * x;
+    if (NORM) acc[J + 1] += x * x;
   }
 #pragma unroll
-  for (int l = 0; l <= J; ++l) {
+  for (int l = 0; l <= J + (NORM ? 1 : 0); ++l) {
     const double bs = block_sum(acc[l]);
     if (threadIdx.x == 0) gpart(P, b, l)[blockIdx.x] = bs;
   }
 }
 
-// w -= sum_l h_l v_l (h = h1 on pass 1, h2 on pass 2); pass 2 also ||w||^2 partials
+// w -= sum_l h_l v_l (h = h1 on pass 1, h2 on pass 2) and ||w||^2 partials (pass 2,
+// when it runs, replaces those of pass 1).  Pass 1 also forms the partial sums of
+// <v_l, w> of the updated w for the second pass while v_l and w are in registers.
 template <int J>
 __device__ __forceinline__ void gaxpy_body(const DevPlan& P, int b, int pass, double* __restrict__ w) {
   const GmresState* st = P.gst + b;
@@ -96,6 +103,9 @@ __device__ __forceinline__ void gaxpy_body(const DevPlan& P, int b, int pass, do
   size_t lo, hi;
   elem_range(P, &lo, &hi);
   double acc = 0.0;
+  double dots[J + 1];
+#pragma unroll
+  for (int l = 0; l <= J; ++l) dots[l] = 0.0;
   for (size_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
     double v[J + 1];
 #pragma unroll
@@ -105,11 +115,20 @@ __device__ __forceinline__ void gaxpy_body(const DevPlan& P, int b, int pass, do
     for (int l = 0; l <= J; ++l) x -= h[l] * v[l];
     ww[e] = x;
     acc += x * x;
+    if (pass == 1) {
+#pragma unroll
+      for (int l = 0; l <= J; ++l) dots[l] += v[l] * x;
+    }
   }
-  if (pass == 2) {
-    const double bs = block_sum(acc);
-    if (threadIdx.x == 0) part_slot(P, PART_RNORM, b)[blockIdx.x] = bs;
+  if (pass == 1 && st->reorth) {
+#pragma unroll
+    for (int l = 0; l <= J; ++l) {
+      const double bd = block_sum(dots[l]);
+      if (threadIdx.x == 0) gpart(P, b, l)[blockIdx.x] = bd;
+    }
   }
+  const double bs = block_sum(acc);
+  if (threadIdx.x == 0) part_slot(P, PART_RNORM, b)[blockIdx.x] = bs;
 }
 
 // t = sum_l y_l v_l, l = 0..J
@@ -144,22 +163,32 @@ __device__ __forceinline__ void gcomb_body(const DevPlan& P, int b, double* __re
 static_assert(kGmresMax == 15, "the dispatch lists one case per Arnoldi column j = 0 .. kGmresMax - 1");
 
 __global__ void __launch_bounds__(kVecThreads)
-k_gdots(DevPlan P, int j, const double* __restrict__ w) {
+k_gdots(DevPlan P, int j, int pass, const double* __restrict__ w) {
   const int b = blockIdx.y;
-  if (P.gst[b].state != ST_RUNNING) return;
-  switch (j) {
+  if (P.gst[b].state != ST_RUNNING || (pass == 2 && !P.gst[b].reorth)) return;
+  if (pass == 1) {
+    switch (j) {
 #define CASE(K) \
-    case K: gdots_body<K>(P, b, w); break;
-    ABAC_GCASES(CASE)
+      case K: gdots_body<K, true>(P, b, w); break;
+      ABAC_GCASES(CASE)
 #undef CASE
-    default: break;
+      default: break;
+    }
+  } else {
+    switch (j) {
+#define CASE(K) \
+      case K: gdots_body<K, false>(P, b, w); break;
+      ABAC_GCASES(CASE)
+#undef CASE
+      default: break;
+    }
   }
 }
 
 __global__ void __launch_bounds__(kVecThreads)
 k_gaxpy(DevPlan P, int j, int pass, double* __restrict__ w) {
   const int b = blockIdx.y;
-  if (P.gst[b].state != ST_RUNNING) return;
+  if (P.gst[b].state != ST_RUNNING || (pass == 2 && !P.gst[b].reorth)) return;
   switch (j) {
 #define CASE(K) \
     case K: gaxpy_body<K>(P, b, pass, w); break;
@@ -250,12 +279,28 @@ k_gfin(DevPlan P, int kind, int nparts, double tol, int maxit, int restart) {
   }
   if (kind == G_DOTS1 || kind == G_DOTS2) {
     const int j = st->k;
+    if (kind == G_DOTS2 && !st->reorth) {   // no second pass: h2 = 0 (set by G_DOTS1)
+      if (threadIdx.x == 0) write_flags(P, b, st);
+      return;
+    }
     double* h = kind == G_DOTS1 ? st->h1 : st->h2;
+    double hh = 0.0;
     for (int l = 0; l <= j; ++l) {
       const double tot = sum_parts(gpart(P, b, l), nparts);
-      if (threadIdx.x == 0) h[l] = tot;
+      if (threadIdx.x == 0) {
+        h[l] = tot;
+        hh += tot * tot;
+      }
     }
+    const double ww = kind == G_DOTS1 ? sum_parts(gpart(P, b, j + 1), nparts) : 0.0;
     if (threadIdx.x == 0) {
+      if (kind == G_DOTS1) {
+        // second pass unless the first kept more than half of ||w||^2
+        const double left = ww - hh;
+        st->reorth = !(left >= 0.5 * ww) || !(ww == ww) ? 1 : 0;
+        if (!st->reorth)
+          for (int l = 0; l <= j; ++l) st->h2[l] = 0.0;
+      }
       st->restart_now = 0;   // the restart copy (if any) has run
       write_flags(P, b, st);
     }
@@ -372,9 +417,9 @@ hipError_t launch_gfin(const DevPlan& P, int kind, double tol, int maxit, int re
   return hipGetLastError();
 }
 
-hipError_t launch_gdots(const DevPlan& P, int j, const double* w, hipStream_t s) {
+hipError_t launch_gdots(const DevPlan& P, int j, int pass, const double* w, hipStream_t s) {
   if (j < 0 || j >= kGmresMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gdots, dim3(update_blocks(P), P.B), dim3(kVecThreads), 0, s, P, j, w);
+  hipLaunchKernelGGL(k_gdots, dim3(update_blocks(P), P.B), dim3(kVecThreads), 0, s, P, j, pass, w);
   return hipGetLastError();
 }
 
