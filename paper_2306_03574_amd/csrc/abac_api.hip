@@ -835,7 +835,7 @@ abac_status abac_gmres_solve(abac_plan* p, const double* f, double* u, double to
     s = enqueue_cinv(p, gslot(P, j), z);
     if (s != ABAC_OK) return s;
     RUN(ABAC_K_STENCIL, launch_stencil(P, STENCIL_T, z, w, nullptr, p->stream));
-    RUN(ABAC_K_GMRES, launch_gdots(P, j, 1, w, p->stream));
+    RUN(ABAC_K_GMRES, launch_gdots(P, j, w, p->stream));
     RUN(ABAC_K_FIN, launch_gfin(P, G_DOTS1, 0.0, 0, 0, p->stream));
     RUN(ABAC_K_GMRES, launch_gaxpy(P, j, 1, w, p->stream));   // also the second pass's dots
     RUN(ABAC_K_FIN, launch_gfin(P, G_DOTS2, 0.0, 0, 0, p->stream));

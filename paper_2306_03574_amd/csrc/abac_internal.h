@@ -225,7 +225,7 @@ hipError_t launch_identity(const DevPlan& P, int mode, const double* in, double*
 enum GmresFin : int { G_INIT = 0, G_DOTS1 = 1, G_DOTS2 = 2, G_NORM = 3, G_CHECK = 4 };
 hipError_t launch_ginit(const DevPlan& P, const double* f, double* u, hipStream_t s);
 hipError_t launch_gfin(const DevPlan& P, int kind, double tol, int maxit, int restart, hipStream_t s);
-hipError_t launch_gdots(const DevPlan& P, int j, int pass, const double* w, hipStream_t s);
+hipError_t launch_gdots(const DevPlan& P, int j, const double* w, hipStream_t s);
 hipError_t launch_gaxpy(const DevPlan& P, int j, int pass, double* w, hipStream_t s);
 hipError_t launch_gnext(const DevPlan& P, const double* w, hipStream_t s);
 hipError_t launch_gbase(const DevPlan& P, const double* src, const double* u, int restart_step, hipStream_t s);

@@ -56,8 +56,9 @@ k_ginit(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
   if (threadIdx.x == 0) part_slot(P, PART_RNORM, b)[blockIdx.x] = bs;
 }
 
-// partial sums of <v_l, w>, l = 0..J, and with NORM also of <w, w> (slot J+1)
-template <int J, bool NORM>
+// partial sums of <v_l, w>, l = 0..J, and of <w, w> (slot J+1), for the first
+// Gram-Schmidt pass (the second pass's dots come from the first update sweep)
+template <int J>
 __device__ __forceinline__ void gdots_body(const DevPlan& P, int b, const double* __restrict__ w) {
   const size_t off = (size_t)b * P.N;
   const double* vs[J + 1];
@@ -76,10 +77,10 @@ __device__ __forceinline__ void gdots_body(const DevPlan& P, int b, const double
     for (int l = 0; l <= J; ++l) v[l] = vs[l][e];
 #pragma unroll
     for (int l = 0; l <= J; ++l) acc[l] += v[l] * x;
-    if (NORM) acc[J + 1] += x * x;
+    acc[J + 1] += x * x;
   }
 #pragma unroll
-  for (int l = 0; l <= J + (NORM ? 1 : 0); ++l) {
+  for (int l = 0; l <= J + 1; ++l) {
     const double bs = block_sum(acc[l]);
     if (threadIdx.x == 0) gpart(P, b, l)[blockIdx.x] = bs;
   }
@@ -163,25 +164,15 @@ __device__ __forceinline__ void gcomb_body(const DevPlan& P, int b, double* __re
 static_assert(kGmresMax == 15, "the dispatch lists one case per Arnoldi column j = 0 .. kGmresMax - 1");
 
 __global__ void __launch_bounds__(kVecThreads)
-k_gdots(DevPlan P, int j, int pass, const double* __restrict__ w) {
+k_gdots(DevPlan P, int j, const double* __restrict__ w) {
   const int b = blockIdx.y;
-  if (P.gst[b].state != ST_RUNNING || (pass == 2 && !P.gst[b].reorth)) return;
-  if (pass == 1) {
-    switch (j) {
+  if (P.gst[b].state != ST_RUNNING) return;
+  switch (j) {
 #define CASE(K) \
-      case K: gdots_body<K, true>(P, b, w); break;
-      ABAC_GCASES(CASE)
+    case K: gdots_body<K>(P, b, w); break;
+    ABAC_GCASES(CASE)
 #undef CASE
-      default: break;
-    }
-  } else {
-    switch (j) {
-#define CASE(K) \
-      case K: gdots_body<K, false>(P, b, w); break;
-      ABAC_GCASES(CASE)
-#undef CASE
-      default: break;
-    }
+    default: break;
   }
 }
 
@@ -417,9 +408,9 @@ hipError_t launch_gfin(const DevPlan& P, int kind, double tol, int maxit, int re
   return hipGetLastError();
 }
 
-hipError_t launch_gdots(const DevPlan& P, int j, int pass, const double* w, hipStream_t s) {
+hipError_t launch_gdots(const DevPlan& P, int j, const double* w, hipStream_t s) {
   if (j < 0 || j >= kGmresMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gdots, dim3(update_blocks(P), P.B), dim3(kVecThreads), 0, s, P, j, pass, w);
+  hipLaunchKernelGGL(k_gdots, dim3(update_blocks(P), P.B), dim3(kVecThreads), 0, s, P, j, w);
   return hipGetLastError();
 }
 
