@@ -78,9 +78,9 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
  * workgroup per time level applies both spatial DSTs (Section 2.3's fast sine
  * transforms) there, so the y passes over memory disappear; their tile and wg[3]
  * follow fixed rules of the shape, since they carry the <q, P^{-1} q> sums
- * (ABAC_SLAB=0 in the environment keeps the separate passes).  wg[5] is 256 when
+ * (ABAC_SLAB=0 in the environment keeps the separate passes).  wg[5] is 512 when
  * small 1D problems (nt * nx <= 4096) run each MINRES iteration as one launch, one
- * 256-thread workgroup per right-hand side doing every step in turn (launch latency,
+ * 512-thread workgroup per right-hand side doing every step in turn (launch latency,
  * not memory, bounds the separate kernels there; ABAC_SMALL=0 keeps them), else 0.  The other tiles are
  * chosen by a tuner that times every legal tile on the plan's own buffers at creation
  * and caches the choice per shape (ABAC_TUNE=0 keeps 256-thread defaults;

@@ -1026,7 +1026,7 @@ abac_status abac_plan_tiles(abac_plan* p, int* wg) {
   wg[2] = p->P.wg_t;
   wg[3] = p->P.wg_xi;
   wg[4] = p->P.wg_s;
-  wg[5] = p->P.small ? 256 : 0;
+  wg[5] = p->P.small ? 512 : 0;
   return ABAC_OK;
 }
 

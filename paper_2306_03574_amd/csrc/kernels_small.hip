@@ -20,7 +20,7 @@ namespace abac {
 
 namespace {
 
-constexpr int kSmallWG = 256;
+constexpr int kSmallWG = 512;
 
 // u = sum_l xm_l z_l over the first nb basis slots (with flush also the two w vectors
 // from their coefficients), the whole right-hand side by one workgroup.
@@ -56,18 +56,36 @@ __device__ __forceinline__ double stencil_small(const DevPlan& P, const double* 
                   : stencil_run<false, OUT, DOT>(P, x, y, f, first, grp, tx, false);
 }
 
+// LDS: the largest tile region of the steps, then the x twiddle table, staged once per
+// launch (the tiles of one workgroup run one after another, so twiddles read from
+// global memory would expose their latency in every FFT pass).
 template <typename T, int L, int NT>
-constexpr size_t small_lds() {
+constexpr size_t small_tile_lds() {
   constexpr size_t a = lds_of<T, L, kSmallWG, TK_XFWD>();
   constexpr size_t b = lds_of<T, L, kSmallWG, TK_XINV>();
   constexpr size_t c = lds_of<T, NT, kSmallWG, TK_TIME>();
-  return a > b ? (a > c ? a : c) : (b > c ? b : c);
+  return ((a > b ? (a > c ? a : c) : (b > c ? b : c)) + 15) / 16 * 16;
+}
+
+template <typename T, int L, int NT>
+constexpr size_t small_lds() {
+  return small_tile_lds<T, L, NT>() + (size_t)L * sizeof(cplx<T>);
+}
+
+template <typename T, int L, int NT>
+__device__ __forceinline__ const cplx<T>* stage_twiddles_small(const DevPlan& P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem + small_tile_lds<T, L, NT>());
+  stage_table(tw, reinterpret_cast<const cplx<T>*>(P.twx), L);
+  __syncthreads();
+  return tw;
 }
 
 template <typename T, int L, int NT>
 constexpr bool small_ok() {
   return tile_ok<T, L, kSmallWG, TK_XFWD>() && tile_ok<T, L, kSmallWG, TK_XINV>() &&
-         tile_ok<T, NT, kSmallWG, TK_TIME>() && (L / 2 - 1) * NT <= 4096;
+         tile_ok<T, NT, kSmallWG, TK_TIME>() && small_lds<T, L, NT>() <= kMaxTransformLds &&
+         (L / 2 - 1) * NT <= 4096 && (sizeof(T) == 4 || NT <= 128);   // FP64 nt = 256 would spill
 }
 
 // One MINRES iteration of right-hand side blockIdx.x (1D, x-DST length L, nt = NT).
@@ -79,6 +97,7 @@ k_iter_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
   const size_t off = (size_t)b * P.N;
   MinresState* st = P.st + b;
   const int tid = threadIdx.x;
+  const cplx<T>* twx = stage_twiddles_small<T, L, NT>(P);
   // matvec q = Y T z_j with <Y T z_j, z_j>, then delta_j
   if (st->state == ST_RUNNING) {
     const int j = st->iter + 1;
@@ -94,7 +113,7 @@ k_iter_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
     const int xtiles = (P.nt + 2 * SX - 1) / (2 * SX);
     const int ttiles = (P.ms / 2 + ST - 1) / ST;
     for (int t = 0; t < xtiles; ++t) {
-      dstx_fwd_tile<T, L, WG>(P, FWD_LANCZOS, nullptr, b, t);
+      dstx_fwd_tile<T, L, WG>(P, FWD_LANCZOS, nullptr, b, t, twx);
       __syncthreads();
     }
     for (int t = 0; t < ttiles; ++t) {
@@ -103,7 +122,7 @@ k_iter_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
     }
     double acc = 0.0;
     for (int t = 0; t < xtiles; ++t) {
-      acc += dstx_inv_tile<T, L, WG>(P, INV_GAMMA_ITER, nullptr, b, t);
+      acc += dstx_inv_tile<T, L, WG>(P, INV_GAMMA_ITER, nullptr, b, t, twx);
       __syncthreads();
     }
     const double tot = block_sum(acc);
@@ -142,6 +161,7 @@ k_setup_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u, d
   const size_t off = (size_t)b * P.N;
   MinresState* st = P.st + b;
   const int tid = threadIdx.x;
+  const cplx<T>* twx = stage_twiddles_small<T, L, NT>(P);
   {
     double acc = 0.0;
     for (int e = tid; e < P.N; e += WG) {
@@ -161,7 +181,7 @@ k_setup_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u, d
     const int xtiles = (P.nt + 2 * SX - 1) / (2 * SX);
     const int ttiles = (P.ms / 2 + ST - 1) / ST;
     for (int t = 0; t < xtiles; ++t) {
-      dstx_fwd_tile<T, L, WG>(P, FWD_PLAIN, P.V[1], b, t);
+      dstx_fwd_tile<T, L, WG>(P, FWD_PLAIN, P.V[1], b, t, twx);
       __syncthreads();
     }
     for (int t = 0; t < ttiles; ++t) {
@@ -170,7 +190,7 @@ k_setup_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u, d
     }
     double acc = 0.0;
     for (int t = 0; t < xtiles; ++t) {
-      acc += dstx_inv_tile<T, L, WG>(P, INV_GAMMA_INIT, nullptr, b, t);
+      acc += dstx_inv_tile<T, L, WG>(P, INV_GAMMA_INIT, nullptr, b, t, twx);
       __syncthreads();
     }
     tot = block_sum(acc);

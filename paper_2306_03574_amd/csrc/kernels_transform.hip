@@ -30,7 +30,7 @@ template <typename T, int L, int WG>
 __global__ void __launch_bounds__(WG)
 k_dstx_fwd(DevPlan P, int mode, int check, const double* __restrict__ in) {
   if ((check || mode == FWD_LANCZOS) && P.st[blockIdx.y].state != ST_RUNNING) return;
-  dstx_fwd_tile<T, L, WG>(P, mode, in, blockIdx.y, blockIdx.x);
+  dstx_fwd_tile<T, L, WG>(P, mode, in, blockIdx.y, blockIdx.x, reinterpret_cast<const cplx<T>*>(P.twx));
 }
 
 template <typename T, int L, int WG>
@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(WG)
 k_dstx_inv(DevPlan P, int mode, double* __restrict__ outp) {
   const int b = blockIdx.y;
   if (mode != INV_PLAIN && P.st[b].state != ST_RUNNING) return;
-  const double acc = dstx_inv_tile<T, L, WG>(P, mode, outp, b, blockIdx.x);
+  const double acc = dstx_inv_tile<T, L, WG>(P, mode, outp, b, blockIdx.x, reinterpret_cast<const cplx<T>*>(P.twx));
   if (mode == INV_PLAIN) return;
   const double bs = block_sum(acc);
   if (threadIdx.x == 0) part_slot(P, PART_GAMMA, b)[blockIdx.x] = bs;

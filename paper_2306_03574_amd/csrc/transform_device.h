@@ -103,9 +103,10 @@ __device__ __forceinline__ void stage_in(TD* dst, const TS* __restrict__ src, in
 // optionally fused with the Lanczos step q = sig_j A Z_j - delta v_j - gamma_j v_{j-1}
 // ---------------------------------------------------------------------------
 // One tile (2 S rows) of right-hand side b; the caller skips stopped right-hand sides.
+// tw: the length-L twiddle table (the plan's, or a copy the caller staged in LDS).
 template <typename T, int L, int WG>
 __device__ __forceinline__ void dstx_fwd_tile(const DevPlan& P, int mode, const double* __restrict__ in, int b,
-                                              int tile) {
+                                              int tile, const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
   constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_of<L, WG>(), Mx = L / 2;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -181,7 +182,7 @@ __device__ __forceinline__ void dstx_fwd_tile(const DevPlan& P, int mode, const 
     v[i] = C{a, c};
   }
   __syncthreads();
-  fft_seq<T, L, false>(v, j, lds + s, S, reinterpret_cast<const C*>(P.twx));
+  fft_seq<T, L, false>(v, j, lds + s, S, tw);
   const T scl = (T)(1.0 / sqrt((double)L));
   // stage the transformed rows ([2S][Mx+1] padded) and write them out contiguously
   __syncthreads();
@@ -424,10 +425,10 @@ __device__ __forceinline__ void time_tile(const DevPlan& P, int inv1, int b, int
 // fused with the partial sums of <q, p>.
 // ---------------------------------------------------------------------------
 // One tile (2 S rows) of right-hand side b; returns this thread's part of <q, p> (0 in
-// INV_PLAIN).  The caller skips stopped right-hand sides.
+// INV_PLAIN).  The caller skips stopped right-hand sides.  tw as for dstx_fwd_tile.
 template <typename T, int L, int WG>
 __device__ __forceinline__ double dstx_inv_tile(const DevPlan& P, int mode, double* __restrict__ outp, int b,
-                                                int tile) {
+                                                int tile, const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
   constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_of<L, WG>(), Mx = L / 2;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -475,7 +476,7 @@ __device__ __forceinline__ double dstx_inv_tile(const DevPlan& P, int mode, doub
     v[i] = C{a, c};
   }
   __syncthreads();
-  fft_seq<T, L, false>(v, j, lds + s, S, reinterpret_cast<const C*>(P.twx));
+  fft_seq<T, L, false>(v, j, lds + s, S, tw);
   const double scl = 1.0 / sqrt((double)L);
   // stage the FP64 rows ([2S][nx+2] padded: odd stride in 8-byte words) and write
   // them out contiguously; with q, accumulate <q, p> in a fixed order for a fixed tile
