@@ -345,6 +345,23 @@ def main():
                 "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": int(bytes_per_launch),
                 "timing": "HIP events around every launch on the plan stream, over a second pass of the same "
                           f"{args.steps} solves ({args.steps / main_run['prof_elapsed']:.2f} solves/s with events on)"}
+    # the preconditioner apply as a whole (MINRES, separate kernels): every transform pass's
+    # time and algorithmic bytes, and the floor-based effective rate (16 N bytes per apply:
+    # read r, write z)
+    pinv = None
+    pinv_classes = [k for k in ("dstx_fwd", "dsty", "time", "dstx_inv") if prof.get(k, {}).get("launches")]
+    if args.solver == "minres" and pinv_classes and "iter" not in abytes:
+        t_s = sum(prof[k]["ms"] for k in pinv_classes) / 1e3
+        b_alg = sum(abytes.get(k, 0) for k in pinv_classes)
+        N = w["nt"] * w["nx"] * max(w["ny"], 1)   # per right-hand side
+        applied = main_run["prof_iters"] + args.steps * B   # applies over all right-hand sides
+        pinv = {"ms_total": round(t_s * 1e3, 3), "rhs_applies": applied,
+                "achieved_GBs": round(b_alg / t_s / 1e9, 1),
+                "frac": round(b_alg / t_s / 1e9 / HBM_PEAK_GBS, 4),
+                "effective_frac": round(16 * N * applied / t_s / 1e9 / HBM_PEAK_GBS, 4),
+                "note": "all transform passes of the preconditioner (Lanczos step and <q, p> fused in), "
+                        "algorithmic bytes over their summed event time; effective_frac counts only 16 "
+                        "bytes per unknown (read r, write z)"}
     kernel_table = {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
                         "GB/s": round(abytes[k] / (v["ms"] / 1e3) / 1e9, 1) if k in abytes and v["ms"] > 0 else None}
                     for k, v in prof.items() if v["launches"]}
@@ -362,6 +379,8 @@ def main():
         "iters": main_run["iters"][:8], "relres_max": max(main_run["relres"]),
         "roofline": roofline, "kernels": kernel_table,
     }
+    if pinv:
+        out["preconditioner_apply"] = pinv
     if not args.no_compare:
         log(f"comparison leg: {other}")
         cmp_run = run_gpu(w, other, max(3, args.steps // 2), 1, args.tol, args.maxit, profile=False,
