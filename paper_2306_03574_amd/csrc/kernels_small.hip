@@ -1,4 +1,5 @@
-// Fused MINRES set-up and iteration for small 1D problems (N = nt * nx <= 4096 unknowns).
+// Fused MINRES set-up, iteration and whole solve for small 1D problems (N = nt * nx <= 4096
+// unknowns).
 //
 // At these sizes an iteration of the separate kernels (matvec, scalar step, three
 // transform passes, scalar step, update, scalar step, iterate, residual, scalar step)
@@ -88,16 +89,17 @@ constexpr bool small_ok() {
          (L / 2 - 1) * NT <= 4096 && (sizeof(T) == 4 || NT <= 128);   // FP64 nt = 256 would spill
 }
 
-// One MINRES iteration of right-hand side blockIdx.x (1D, x-DST length L, nt = NT).
+// One MINRES iteration of right-hand side blockIdx.x (1D, x-DST length L, nt = NT); every
+// thread of the workgroup calls it, and every branch below is uniform (state read after a
+// barrier).
 template <typename T, int L, int NT>
-__global__ void __launch_bounds__(kSmallWG)
-k_iter_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
+__device__ __noinline__ void iter_small(const DevPlan& P, const double* __restrict__ f, double* __restrict__ u,
+                                        const cplx<T>* twx) {
   constexpr int WG = kSmallWG;
   const int b = blockIdx.x;
   const size_t off = (size_t)b * P.N;
   MinresState* st = P.st + b;
   const int tid = threadIdx.x;
-  const cplx<T>* twx = stage_twiddles_small<T, L, NT>(P);
   // matvec q = Y T z_j with <Y T z_j, z_j>, then delta_j
   if (st->state == ST_RUNNING) {
     const int j = st->iter + 1;
@@ -150,6 +152,26 @@ k_iter_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
   }
 }
 
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(kSmallWG)
+k_iter_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
+  iter_small<T, L, NT>(P, f, u, stage_twiddles_small<T, L, NT>(P));
+}
+
+// Whole solve after the set-up: iterations until the right-hand side stops (converged,
+// maxit, breakdown), at most max_iters.  Each iteration still posts its snapshot.
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(kSmallWG)
+k_solve_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u, int max_iters) {
+  const cplx<T>* twx = stage_twiddles_small<T, L, NT>(P);
+  const MinresState* st = P.st + blockIdx.x;
+  for (int it = 0; it < max_iters; ++it) {
+    __syncthreads();   // the previous iteration's state is visible to every thread
+    if (st->state != ST_RUNNING) break;
+    iter_small<T, L, NT>(P, f, u, twx);
+  }
+}
+
 // Set-up of a solve of right-hand side blockIdx.x in one workgroup: b = Y f into v_1,
 // u = 0, ||b||^2, then z_1 = P^{-1} b and gamma_1 (the separate kernels' set-up and
 // first preconditioner apply, in the same order and under the same conditions).
@@ -198,15 +220,18 @@ k_setup_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u, d
   if (fin_begin(P, b, FIN_GAMMA_INIT) && tid == 0) fin_scalar(P, b, FIN_GAMMA_INIT, tot, 0.0, 0);
 }
 
+// what: 0 one iteration, 1 the set-up, 2 the iterations of a whole solve (at most maxit)
 template <typename T, int L, int NT>
-hipError_t launch_small_t(const DevPlan& P, const double* f, double* u, hipStream_t s, bool setup, double tol,
+hipError_t launch_small_t(const DevPlan& P, const double* f, double* u, hipStream_t s, int what, double tol,
                           int maxit) {
   if constexpr (!small_ok<T, L, NT>()) {
     return hipErrorInvalidValue;
   } else {
     constexpr size_t lds = small_lds<T, L, NT>();
-    if (setup)
+    if (what == 1)
       hipLaunchKernelGGL((k_setup_small<T, L, NT>), dim3(P.B), dim3(kSmallWG), lds, s, P, f, u, tol, maxit);
+    else if (what == 2)
+      hipLaunchKernelGGL((k_solve_small<T, L, NT>), dim3(P.B), dim3(kSmallWG), lds, s, P, f, u, maxit);
     else
       hipLaunchKernelGGL((k_iter_small<T, L, NT>), dim3(P.B), dim3(kSmallWG), lds, s, P, f, u);
     return hipGetLastError();
@@ -225,9 +250,9 @@ hipError_t launch_small_t(const DevPlan& P, const double* f, double* u, hipStrea
   }
 
 template <typename T>
-hipError_t small_dispatch(const DevPlan& P, const double* f, double* u, hipStream_t s, bool setup, double tol,
+hipError_t small_dispatch(const DevPlan& P, const double* f, double* u, hipStream_t s, int what, double tol,
                           int maxit) {
-#define CALL(LL, NN) launch_small_t<T, LL, NN>(P, f, u, s, setup, tol, maxit)
+#define CALL(LL, NN) launch_small_t<T, LL, NN>(P, f, u, s, what, tol, maxit)
   switch (2 * P.Mx) {
     case 16: ABAC_SMALL_NT(16, CALL)
     case 32: ABAC_SMALL_NT(32, CALL)
@@ -263,13 +288,18 @@ bool small_valid_t(int L, int nt) {
 }  // namespace
 
 hipError_t launch_iter_small(const DevPlan& P, int prec, const double* f, double* u, hipStream_t s) {
-  return prec ? small_dispatch<float>(P, f, u, s, false, 0.0, 0) : small_dispatch<double>(P, f, u, s, false, 0.0, 0);
+  return prec ? small_dispatch<float>(P, f, u, s, 0, 0.0, 0) : small_dispatch<double>(P, f, u, s, 0, 0.0, 0);
 }
 
 hipError_t launch_setup_small(const DevPlan& P, int prec, const double* f, double* u, double tol, int maxit,
                               hipStream_t s) {
-  return prec ? small_dispatch<float>(P, f, u, s, true, tol, maxit)
-              : small_dispatch<double>(P, f, u, s, true, tol, maxit);
+  return prec ? small_dispatch<float>(P, f, u, s, 1, tol, maxit) : small_dispatch<double>(P, f, u, s, 1, tol, maxit);
+}
+
+hipError_t launch_solve_small(const DevPlan& P, int prec, const double* f, double* u, int max_iters,
+                              hipStream_t s) {
+  return prec ? small_dispatch<float>(P, f, u, s, 2, 0.0, max_iters)
+              : small_dispatch<double>(P, f, u, s, 2, 0.0, max_iters);
 }
 
 bool small_path_valid(int nx, int ny, int nt, int prec) {

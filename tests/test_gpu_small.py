@@ -124,3 +124,24 @@ def test_fused_variable_coefficient(monkeypatch):
         res.append((_host(u)[0], iters[0], status[0]))
     assert res[0][2] == res[1][2] == 0 and res[0][1] == res[1][1]
     assert _rel(res[0][0], res[1][0]) < 1e-10
+
+
+def test_async_iterations_match_the_single_launch_solve(monkeypatch):
+    """A synchronous solve runs all iterations in one launch; the asynchronous interface
+    launches one iteration at a time.  Both run the same iteration body: bitwise equal."""
+    nx, nt, alpha = 63, 64, 1e-2
+    g = Grid(nx, 0, nt)
+    src, psi0, psi1 = synth.random_source(nx, 0, nt, seed=81)
+    f = _dev(aao.build_rhs(g, src, psi0, psi1)[None])
+    p = _plan(nx, nt, alpha=alpha, monkeypatch=monkeypatch)
+    assert p.tiles()["small"] > 0
+    u1, it1, rr1, st1 = p.solve(f, tol=1e-8, maxit=100)
+    u2 = torch.empty_like(u1)
+    p.begin(f, u2, tol=1e-8, maxit=100)
+    for _ in range(100):
+        p.advance(1)
+        if p.poll():
+            break
+    it2, rr2, st2 = p.finish()
+    assert it1 == it2 and st1 == st2 == [0] and rr1 == rr2
+    assert torch.equal(u1, u2)
