@@ -79,10 +79,9 @@ def algorithmic_bytes(w, prec, iters_total, solves, fused=False):
       form      8 (k+1) N      (read z_1..z_k, write u) once per solve of k <= 12
                                iterations (the convergence check)
       init      24 N           (read f; write v1 = r0, u) per solve
-    With `fused` (small 1D plans, one workgroup per right-hand side runs the set-up and
-    each whole iteration) the per-iteration bytes above, and the iterate formed at the
-    check, are the "iter" class, and the set-up with its first preconditioner apply is
-    the "init" class.
+    With `fused` (small 1D plans: one launch per solve, one workgroup per right-hand side
+    runs the set-up with its first preconditioner apply and every iteration) all of the
+    above is the "iter" class.
     """
     nx, ny, nt = w["nx"], w["ny"], w["nt"]
     N = nt * nx * max(ny, 1)
@@ -91,10 +90,8 @@ def algorithmic_bytes(w, prec, iters_total, solves, fused=False):
     applies = iters_total + solves
     if fused:
         per_iter = 16 * N + (32 * N + s * NS) + 2 * s * NS + (s * NS + 16 * N) + 24 * N
-        return {
-            "iter": per_iter * iters_total + 8 * N * (iters_total + solves),
-            "init": (24 * N + (8 * N + s * NS) + 2 * s * NS + (s * NS + 16 * N)) * solves,
-        }
+        setup = 24 * N + (8 * N + s * NS) + 2 * s * NS + (s * NS + 16 * N)
+        return {"iter": per_iter * iters_total + 8 * N * (iters_total + solves) + setup * solves}
     return {
         "stencil": 16 * N * iters_total,
         "dstx_fwd": (32 * N + s * NS) * iters_total + (8 * N + s * NS) * solves,

@@ -952,14 +952,17 @@ abac_status abac_minres_finish(abac_plan* p, int* iters, double* relres, int* st
 
 abac_status abac_minres_solve(abac_plan* p, const double* f, double* u, double tol, int maxit, int* iters,
                               double* relres, int* status) {
-  abac_status s = abac_minres_begin(p, f, u, tol, maxit);
-  if (s != ABAC_OK) return s;
-  if (p->P.small) {
-    // small problems: every iteration of the solve in one launch (the state machine stops
-    // each right-hand side by maxit at the latest; the bound is a safety net)
-    RUN(ABAC_K_ITER, launch_solve_small(p->P, p->prec, p->f, p->u, maxit + 1, p->stream));
+  if (p && p->P.small && f && u && f != u && tol > 0 && maxit >= 1) {
+    // small problems: the set-up and every iteration in one launch
+    p->f = f;
+    p->u = u;
+    p->active = true;
+    p->ring_posted = 0;
+    RUN(ABAC_K_ITER, launch_solve_small(p->P, p->prec, f, u, tol, maxit, p->stream));
     return abac_minres_finish(p, iters, relres, status);
   }
+  abac_status s = abac_minres_begin(p, f, u, tol, maxit);
+  if (s != ABAC_OK) return s;
   // Keep up to kAhead iterations queued beyond the newest observed state while the
   // observed residual decay predicts that convergence is further away; near the
   // predicted stop, step one iteration at a time so no idle iterations are queued.

@@ -254,7 +254,7 @@ int slab_wg(int nx, int ny, int prec, int maxlds, size_t margin);
 hipError_t launch_iter_small(const DevPlan& P, int prec, const double* f, double* u, hipStream_t s);
 hipError_t launch_setup_small(const DevPlan& P, int prec, const double* f, double* u, double tol, int maxit,
                               hipStream_t s);
-hipError_t launch_solve_small(const DevPlan& P, int prec, const double* f, double* u, int max_iters,
+hipError_t launch_solve_small(const DevPlan& P, int prec, const double* f, double* u, double tol, int maxit,
                               hipStream_t s);
 bool small_path_valid(int nx, int ny, int nt, int prec);
 // transform kernel kinds (tile validity and LDS size differ per kind)

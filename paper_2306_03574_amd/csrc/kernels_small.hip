@@ -158,32 +158,18 @@ k_iter_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u) {
   iter_small<T, L, NT>(P, f, u, stage_twiddles_small<T, L, NT>(P));
 }
 
-// Whole solve after the set-up: iterations until the right-hand side stops (converged,
-// maxit, breakdown), at most max_iters.  Each iteration still posts its snapshot.
-template <typename T, int L, int NT>
-__global__ void __launch_bounds__(kSmallWG)
-k_solve_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u, int max_iters) {
-  const cplx<T>* twx = stage_twiddles_small<T, L, NT>(P);
-  const MinresState* st = P.st + blockIdx.x;
-  for (int it = 0; it < max_iters; ++it) {
-    __syncthreads();   // the previous iteration's state is visible to every thread
-    if (st->state != ST_RUNNING) break;
-    iter_small<T, L, NT>(P, f, u, twx);
-  }
-}
 
 // Set-up of a solve of right-hand side blockIdx.x in one workgroup: b = Y f into v_1,
 // u = 0, ||b||^2, then z_1 = P^{-1} b and gamma_1 (the separate kernels' set-up and
 // first preconditioner apply, in the same order and under the same conditions).
 template <typename T, int L, int NT>
-__global__ void __launch_bounds__(kSmallWG)
-k_setup_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u, double tol, int maxit) {
+__device__ __noinline__ void setup_small(const DevPlan& P, const double* __restrict__ f, double* __restrict__ u,
+                                         double tol, int maxit, const cplx<T>* twx) {
   constexpr int WG = kSmallWG;
   const int b = blockIdx.x;
   const size_t off = (size_t)b * P.N;
   MinresState* st = P.st + b;
   const int tid = threadIdx.x;
-  const cplx<T>* twx = stage_twiddles_small<T, L, NT>(P);
   {
     double acc = 0.0;
     for (int e = tid; e < P.N; e += WG) {
@@ -220,7 +206,28 @@ k_setup_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u, d
   if (fin_begin(P, b, FIN_GAMMA_INIT) && tid == 0) fin_scalar(P, b, FIN_GAMMA_INIT, tot, 0.0, 0);
 }
 
-// what: 0 one iteration, 1 the set-up, 2 the iterations of a whole solve (at most maxit)
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(kSmallWG)
+k_setup_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u, double tol, int maxit) {
+  setup_small<T, L, NT>(P, f, u, tol, maxit, stage_twiddles_small<T, L, NT>(P));
+}
+
+// A whole solve in one launch: the set-up, then iterations until the right-hand side
+// stops (at most maxit + 1, a safety net: the state machine stops it by maxit).
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(kSmallWG)
+k_solve_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u, double tol, int maxit) {
+  const cplx<T>* twx = stage_twiddles_small<T, L, NT>(P);
+  setup_small<T, L, NT>(P, f, u, tol, maxit, twx);
+  const MinresState* st = P.st + blockIdx.x;
+  for (int it = 0; it <= maxit; ++it) {
+    __syncthreads();   // the previous step's state is visible to every thread
+    if (st->state != ST_RUNNING) break;
+    iter_small<T, L, NT>(P, f, u, twx);
+  }
+}
+
+// what: 0 one iteration, 1 the set-up, 2 a whole solve (set-up and iterations)
 template <typename T, int L, int NT>
 hipError_t launch_small_t(const DevPlan& P, const double* f, double* u, hipStream_t s, int what, double tol,
                           int maxit) {
@@ -231,7 +238,7 @@ hipError_t launch_small_t(const DevPlan& P, const double* f, double* u, hipStrea
     if (what == 1)
       hipLaunchKernelGGL((k_setup_small<T, L, NT>), dim3(P.B), dim3(kSmallWG), lds, s, P, f, u, tol, maxit);
     else if (what == 2)
-      hipLaunchKernelGGL((k_solve_small<T, L, NT>), dim3(P.B), dim3(kSmallWG), lds, s, P, f, u, maxit);
+      hipLaunchKernelGGL((k_solve_small<T, L, NT>), dim3(P.B), dim3(kSmallWG), lds, s, P, f, u, tol, maxit);
     else
       hipLaunchKernelGGL((k_iter_small<T, L, NT>), dim3(P.B), dim3(kSmallWG), lds, s, P, f, u);
     return hipGetLastError();
@@ -296,10 +303,9 @@ hipError_t launch_setup_small(const DevPlan& P, int prec, const double* f, doubl
   return prec ? small_dispatch<float>(P, f, u, s, 1, tol, maxit) : small_dispatch<double>(P, f, u, s, 1, tol, maxit);
 }
 
-hipError_t launch_solve_small(const DevPlan& P, int prec, const double* f, double* u, int max_iters,
+hipError_t launch_solve_small(const DevPlan& P, int prec, const double* f, double* u, double tol, int maxit,
                               hipStream_t s) {
-  return prec ? small_dispatch<float>(P, f, u, s, 2, 0.0, max_iters)
-              : small_dispatch<double>(P, f, u, s, 2, 0.0, max_iters);
+  return prec ? small_dispatch<float>(P, f, u, s, 2, tol, maxit) : small_dispatch<double>(P, f, u, s, 2, tol, maxit);
 }
 
 bool small_path_valid(int nx, int ny, int nt, int prec) {

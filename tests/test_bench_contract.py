@@ -39,13 +39,13 @@ def test_byte_model_per_unit_figures():
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_fused_iteration_byte_model_moves_the_same_bytes(prec):
-    """The fused small-problem iteration does the same passes: its classes add up to the
+    """The fused small-problem solve does the same passes: its one class adds up to the
     separate kernels' total."""
     w = bench.WORKLOADS["wave1d_63x64"]
     sep = bench.algorithmic_bytes(w, prec, iters_total=37, solves=5)
     fus = bench.algorithmic_bytes(w, prec, iters_total=37, solves=5, fused=True)
     assert sum(sep.values()) == sum(fus.values())
-    assert set(fus) == {"iter", "init"}
+    assert set(fus) == {"iter"}
 
 
 def _write_counters(path, rows):
