@@ -810,7 +810,6 @@ abac_status abac_gmres_solve(abac_plan* p, const double* f, double* u, double to
   const DevPlan& P = p->P;
   const int B = P.B;
   double* z = P.V[0];
-  double* w = P.V[1];
   double* t = P.V[2];
   std::vector<GmresFlags> fl(B);
   auto read_flags = [&]() -> abac_status {
@@ -834,6 +833,7 @@ abac_status abac_gmres_solve(abac_plan* p, const double* f, double* u, double to
   while (any([](const GmresFlags& x) { return x.state == ST_RUNNING; })) {
     s = enqueue_cinv(p, gslot(P, j), z);
     if (s != ABAC_OK) return s;
+    double* w = gslot(P, j + 1);   // w is formed in the slot of v_{j+1}, which stays unnormalised
     RUN(ABAC_K_STENCIL, launch_stencil(P, STENCIL_T, z, w, nullptr, p->stream));
     RUN(ABAC_K_GMRES, launch_gdots(P, j, w, p->stream));
     RUN(ABAC_K_FIN, launch_gfin(P, G_DOTS1, 0.0, 0, 0, p->stream));
@@ -841,7 +841,6 @@ abac_status abac_gmres_solve(abac_plan* p, const double* f, double* u, double to
     RUN(ABAC_K_FIN, launch_gfin(P, G_DOTS2, 0.0, 0, 0, p->stream));
     RUN(ABAC_K_GMRES, launch_gaxpy(P, j, 2, w, p->stream));
     RUN(ABAC_K_FIN, launch_gfin(P, G_NORM, 0.0, 0, 0, p->stream));
-    RUN(ABAC_K_GMRES, launch_gnext(P, w, p->stream));
     if ((s = read_flags()) != ABAC_OK) return s;
     if (!any([](const GmresFlags& x) { return x.state == ST_RUNNING && x.need; })) {
       ++j;

@@ -69,6 +69,7 @@ struct GmresState {
   double g[kGmresMax + 1];                 // rotated beta e_1
   double y[kGmresMax];                     // least-squares solution (when forming u)
   double h1[kGmresMax + 1], h2[kGmresMax + 1];   // the two Gram-Schmidt passes of a column
+  double sig[kGmresMax + 1];                 // v_l = sig_l * (slot l): slots hold unnormalised vectors
   double bnorm2, tol2, scale, res2, resid2;
   int iter, k, maxit, restart, state, status, need, explicit_mode, restart_now;
   int reorth;   // the current column needs the second Gram-Schmidt pass
@@ -227,7 +228,6 @@ hipError_t launch_ginit(const DevPlan& P, const double* f, double* u, hipStream_
 hipError_t launch_gfin(const DevPlan& P, int kind, double tol, int maxit, int restart, hipStream_t s);
 hipError_t launch_gdots(const DevPlan& P, int j, const double* w, hipStream_t s);
 hipError_t launch_gaxpy(const DevPlan& P, int j, int pass, double* w, hipStream_t s);
-hipError_t launch_gnext(const DevPlan& P, const double* w, hipStream_t s);
 hipError_t launch_gbase(const DevPlan& P, const double* src, const double* u, int restart_step, hipStream_t s);
 hipError_t launch_gcomb(const DevPlan& P, int j, double* t, hipStream_t s);
 hipError_t launch_gaddx(const DevPlan& P, double* u, const double* z, hipStream_t s);

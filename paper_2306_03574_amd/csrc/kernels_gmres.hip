@@ -11,6 +11,9 @@
 //   arithmetic); the dots of the second pass ride along with the update of the first;
 //   fixed-order sums;
 //   H(:, j) = h1 + h2, H(j+1, j) = ||w||;  Givens rotations;  v_{j+1} = w / ||w||.
+// Slot l holds v_l / sig_l: w is formed in the slot of v_{j+1} from the unnormalised
+// v_j, so its coefficients carry the factor sig_j, and v_{j+1} = w / ||w|| is never
+// written out (sig_{j+1} = 1 / ||w||).  Slot 0 is written normalised (sig_0 = 1).
 // When the rotated residual meets tol, the cycle ends or maxit is reached, the iterate
 // u = X0 + C^{-1}(V y) is formed (X0: the iterate at the start of the cycle) and the
 // residual f - T u is checked explicitly; at the end of a cycle the next one starts
@@ -98,7 +101,7 @@ __device__ __forceinline__ void gaxpy_body(const DevPlan& P, int b, int pass, do
 #pragma unroll
   for (int l = 0; l <= J; ++l) {
     vs[l] = gslot(P, l) + off;
-    h[l] = pass == 1 ? st->h1[l] : st->h2[l];
+    h[l] = (pass == 1 ? st->h1[l] : st->h2[l]) * st->sig[l];
   }
   double* ww = w + off;
   size_t lo, hi;
@@ -142,7 +145,7 @@ __device__ __forceinline__ void gcomb_body(const DevPlan& P, int b, double* __re
 #pragma unroll
   for (int l = 0; l <= J; ++l) {
     vs[l] = gslot(P, l) + off;
-    y[l] = st->y[l];
+    y[l] = st->y[l] * st->sig[l];
   }
   double* tt = t + off;
   size_t lo, hi;
@@ -201,20 +204,6 @@ k_gcomb(DevPlan P, int j, double* __restrict__ t) {
 #undef CASE
     default: break;
   }
-}
-
-// v_{k} = w * scale after a step (k = the new column count of the cycle)
-__global__ void __launch_bounds__(kVecThreads)
-k_gnext(DevPlan P, const double* __restrict__ w) {
-  const int b = blockIdx.y;
-  const GmresState* st = P.gst + b;
-  if (st->state != ST_RUNNING || st->k > kGmresMax) return;
-  const size_t off = (size_t)b * P.N;
-  double* v = gslot(P, st->k) + off;
-  const double sc = st->scale;
-  size_t lo, hi;
-  elem_range(P, &lo, &hi);
-  for (size_t e = lo + threadIdx.x; e < hi; e += blockDim.x) v[e] = w[off + e] * sc;
 }
 
 // v_0 = src * scale: at set-up (src = v_0 itself) for running right-hand sides, or at a
@@ -277,7 +266,7 @@ k_gfin(DevPlan P, int kind, int nparts, double tol, int maxit, int restart) {
     double* h = kind == G_DOTS1 ? st->h1 : st->h2;
     double hh = 0.0;
     for (int l = 0; l <= j; ++l) {
-      const double tot = sum_parts(gpart(P, b, l), nparts);
+      const double tot = sum_parts(gpart(P, b, l), nparts) * st->sig[l];
       if (threadIdx.x == 0) {
         h[l] = tot;
         hh += tot * tot;
@@ -322,6 +311,7 @@ k_gfin(DevPlan P, int kind, int nparts, double tol, int maxit, int restart) {
         st->state = ST_RUNNING;
         st->g[0] = sqrt(tot);
         st->scale = 1.0 / st->g[0];
+        st->sig[0] = 1.0;
       }
       break;
     case G_NORM: {
@@ -331,10 +321,12 @@ k_gfin(DevPlan P, int kind, int nparts, double tol, int maxit, int restart) {
         st->status = -5;   // ABAC_EBREAKDOWN
         break;
       }
-      const double hn = sqrt(tot);
+      const double hn = sqrt(tot);   // of w formed from the unnormalised v_j: times sig_j below
       double* col = st->H + (size_t)j * (kGmresMax + 1);
-      for (int l = 0; l <= j; ++l) col[l] = st->h1[l] + st->h2[l];
-      col[j + 1] = hn;
+      const double sj = st->sig[j];
+      for (int l = 0; l <= j; ++l) col[l] = sj * (st->h1[l] + st->h2[l]);
+      col[j + 1] = sj * hn;
+      st->sig[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
       for (int l = 0; l < j; ++l) {   // earlier rotations on the new column
         const double t = st->cs[l] * col[l] + st->sn[l] * col[l + 1];
         col[l + 1] = -st->sn[l] * col[l] + st->cs[l] * col[l + 1];
@@ -350,7 +342,6 @@ k_gfin(DevPlan P, int kind, int nparts, double tol, int maxit, int restart) {
       st->g[j] = c * st->g[j];
       st->iter += 1;
       st->k = j + 1;
-      st->scale = hn > 0.0 ? 1.0 / hn : 0.0;
       st->resid2 = st->g[j + 1] * st->g[j + 1];
       st->need = st->resid2 <= st->tol2 * st->bnorm2 || st->explicit_mode || st->k == st->restart ||
                  st->iter >= st->maxit || hn == 0.0;
@@ -385,6 +376,7 @@ k_gfin(DevPlan P, int kind, int nparts, double tol, int maxit, int restart) {
         for (int l = 0; l <= kGmresMax; ++l) st->g[l] = 0.0;
         st->g[0] = sqrt(tot);
         st->scale = 1.0 / st->g[0];
+        st->sig[0] = 1.0;
       } else {
         st->explicit_mode = 1;   // the rotated residual was optimistic: check every step
       }
@@ -417,11 +409,6 @@ hipError_t launch_gdots(const DevPlan& P, int j, const double* w, hipStream_t s)
 hipError_t launch_gaxpy(const DevPlan& P, int j, int pass, double* w, hipStream_t s) {
   if (j < 0 || j >= kGmresMax) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_gaxpy, dim3(update_blocks(P), P.B), dim3(kVecThreads), 0, s, P, j, pass, w);
-  return hipGetLastError();
-}
-
-hipError_t launch_gnext(const DevPlan& P, const double* w, hipStream_t s) {
-  hipLaunchKernelGGL(k_gnext, dim3(update_blocks(P), P.B), dim3(kVecThreads), 0, s, P, w);
   return hipGetLastError();
 }
 
