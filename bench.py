@@ -30,6 +30,9 @@ WORKLOADS = {
     "wave2d_511x511x512": dict(nx=511, ny=511, nt=512, alpha=1e-3, batch=1, source="gaussian_field"),
     "batch64_wave2d_127x127x128": dict(nx=127, ny=127, nt=128, alpha=1e-3, batch=64, source="jacobi"),
     "wave1d_63x64": dict(nx=63, ny=0, nt=64, alpha=1e-3, batch=1, source="manufactured1d"),
+    # the same 1D problem as a batch (throughput of the launch-bound size): right-hand
+    # side b draws its noise with seed 1 + b, so b = 0 is the single-solve workload
+    "batch256_wave1d_63x64": dict(nx=63, ny=0, nt=64, alpha=1e-3, batch=256, source="manufactured1d"),
     "serving_mix": dict(nx=0, ny=0, nt=0, alpha=0.0, batch=1, source="serving"),
 }
 KERNEL_CLASSES = ["stencil", "dstx_fwd", "dsty", "time", "dstx_inv", "update", "form", "residual", "init", "rhs", "fin",
@@ -48,7 +51,7 @@ def make_inputs(w):
         if w["source"] == "manufactured2d":
             src, p0, p1, _ = synth.manufactured_2d(nx, ny, nt)
         elif w["source"] == "manufactured1d":
-            src, p0, p1, _ = synth.manufactured_1d(nx, nt, noise_std=0.1, seed=1)
+            src, p0, p1, _ = synth.manufactured_1d(nx, nt, noise_std=0.1, seed=1 + b)
         elif w["source"] == "gaussian_field":
             src, p0, p1 = synth.gaussian_field_source(nx, ny, nt, seed=3)
         elif w["source"] == "jacobi":
