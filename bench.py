@@ -27,6 +27,9 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     # name: nx, ny, nt, alpha, batch, source recipe
     "wave2d_255x255x256": dict(nx=255, ny=255, nt=256, alpha=1e-3, batch=1, source="manufactured2d"),
+    # the same grid with an i.i.d. N(0,1) source (seed 2) and zero initial data: a
+    # right-hand side without the manufactured solution's smoothness
+    "wave2d_255x255x256_random": dict(nx=255, ny=255, nt=256, alpha=1e-3, batch=1, source="random", seed=2),
     "wave2d_511x511x512": dict(nx=511, ny=511, nt=512, alpha=1e-3, batch=1, source="gaussian_field"),
     "batch64_wave2d_127x127x128": dict(nx=127, ny=127, nt=128, alpha=1e-3, batch=64, source="jacobi"),
     "wave1d_63x64": dict(nx=63, ny=0, nt=64, alpha=1e-3, batch=1, source="manufactured1d"),
@@ -52,6 +55,8 @@ def make_inputs(w):
             src, p0, p1, _ = synth.manufactured_2d(nx, ny, nt)
         elif w["source"] == "manufactured1d":
             src, p0, p1, _ = synth.manufactured_1d(nx, nt, noise_std=0.1, seed=1 + b)
+        elif w["source"] == "random":
+            src, p0, p1 = synth.random_source(nx, ny, nt, seed=w["seed"] + b)
         elif w["source"] == "gaussian_field":
             src, p0, p1 = synth.gaussian_field_source(nx, ny, nt, seed=3)
         elif w["source"] == "jacobi":
@@ -334,6 +339,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="wave2d_255x255x256", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default=None, choices=["fp64", "fp32"])
+    ap.add_argument("--alpha", type=float, default=None, help="override the workload's alpha")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -358,7 +364,9 @@ def main():
     if args.workload == "serving_mix":
         run_serving(args)
         return
-    w = WORKLOADS[args.workload]
+    w = dict(WORKLOADS[args.workload])
+    if args.alpha is not None:
+        w["alpha"] = args.alpha
     prec = args.prec or ("fp32" if args.workload == "wave2d_511x511x512" else "fp64")
     other = "fp32" if prec == "fp64" else "fp64"
     log(f"workload {args.workload} prec {prec} steps {args.steps} warmup {args.warmup}")
