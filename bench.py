@@ -155,11 +155,13 @@ def source_sha():
 COPY_PROBE_BYTES = 1 << 30
 
 
-def copy_probe():
+def copy_probe(nbytes=None):
     """A plain device copy of COPY_PROBE_BYTES (read and written once per dispatch):
-    the calibration run for the HBM byte counters.  Prints its own bandwidth."""
+    the calibration run for the HBM byte counters.  Prints its own bandwidth.  Another
+    size (nbytes) gives the copy ceiling at that size."""
     import torch
-    a = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    nbytes = nbytes or COPY_PROBE_BYTES
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
@@ -169,7 +171,7 @@ def copy_probe():
         b.copy_(a)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / n
-    print(json.dumps({"copy_bytes": COPY_PROBE_BYTES, "GB/s": round(2 * COPY_PROBE_BYTES / dt / 1e9, 1)}), flush=True)
+    print(json.dumps({"copy_bytes": nbytes, "GB/s": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
 
 
 def run_gpu(w, prec, steps, warmup, tol, maxit, profile=True, solver="minres", restart=15):
@@ -349,13 +351,14 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=160.0, help="serving: HBM budget")
     ap.add_argument("--max-active", type=int, default=16, help="serving: concurrent solves")
     ap.add_argument("--copy-probe", action="store_true", help="only run the HBM counter calibration copy")
+    ap.add_argument("--copy-gib", type=float, default=None, help="copy probe: buffer size in GiB (default 1)")
     ap.add_argument("--solver", default="minres", choices=["minres", "gmres"],
                     help="minres: Y T u = Y f with the ABAC preconditioner (the method); gmres: T u = f "
                          "right-preconditioned by the block alpha-circulant C_alpha")
     ap.add_argument("--restart", type=int, default=15, help="gmres: restart length (<= 15)")
     args = ap.parse_args()
     if args.copy_probe:
-        copy_probe()
+        copy_probe(int(args.copy_gib * (1 << 30)) // 8 * 8 if args.copy_gib else None)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single GPU and sharding one solve over "
