@@ -217,14 +217,23 @@ k_setup_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u, d
 template <typename T, int L, int NT>
 __global__ void __launch_bounds__(kSmallWG)
 k_solve_small(DevPlan P, const double* __restrict__ f, double* __restrict__ u, double tol, int maxit) {
-  const cplx<T>* twx = stage_twiddles_small<T, L, NT>(P);
-  setup_small<T, L, NT>(P, f, u, tol, maxit, twx);
-  const MinresState* st = P.st + blockIdx.x;
+  // The right-hand side's scalar state stays in LDS for the whole solve (the scalar steps
+  // and every thread's state tests read it many times per iteration) and goes back to
+  // memory at the end.  Q addresses it as Q.st + blockIdx.x, like the kernels' state.
+  __shared__ MinresState st_lds;
+  const int b = blockIdx.x;
+  if (threadIdx.x == 0) st_lds = P.st[b];
+  DevPlan Q = P;
+  Q.st = reinterpret_cast<MinresState*>(reinterpret_cast<uintptr_t>(&st_lds) - (uintptr_t)b * sizeof(MinresState));
+  const cplx<T>* twx = stage_twiddles_small<T, L, NT>(Q);   // its barrier also publishes st_lds
+  setup_small<T, L, NT>(Q, f, u, tol, maxit, twx);
   for (int it = 0; it <= maxit; ++it) {
     __syncthreads();   // the previous step's state is visible to every thread
-    if (st->state != ST_RUNNING) break;
-    iter_small<T, L, NT>(P, f, u, twx);
+    if (st_lds.state != ST_RUNNING) break;
+    iter_small<T, L, NT>(Q, f, u, twx);
   }
+  __syncthreads();
+  if (threadIdx.x == 0) P.st[b] = st_lds;
 }
 
 // what: 0 one iteration, 1 the set-up, 2 a whole solve (set-up and iterations)
