@@ -131,7 +131,7 @@ ABAC_FFT_SHAPE(32, 4, 2, 0)
 ABAC_FFT_SHAPE(64, 8, 0, 0)
 ABAC_FFT_SHAPE(128, 8, 2, 0)
 ABAC_FFT_SHAPE(256, 16, 0, 0)
-ABAC_FFT_SHAPE(512, 16, 2, 0)
+ABAC_FFT_SHAPE(512, 8, 8, 0)
 ABAC_FFT_SHAPE(1024, 16, 4, 0)
 ABAC_FFT_SHAPE(2048, 16, 8, 0)
 ABAC_FFT_SHAPE(4096, 16, 16, 0)
