@@ -84,3 +84,20 @@ def test_counter_calibration_and_per_launch_traffic(tmp_path):
     assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == pytest.approx(1.0)
     assert rec["source_sha"] == profiling.source_sha()
     assert rec["bytes_per_launch"] == pytest.approx(3 * (1 << 30))
+
+
+def test_input_recipes_of_the_derived_workloads():
+    """The random-source twin draws N(0,1) with seed 2 and zero initial data; the batched 1D
+    workload's right-hand side b uses noise seed 1 + b, so b = 0 is the single-solve input."""
+    import numpy as np
+    import synth
+    tw = bench.WORKLOADS["wave2d_255x255x256_random"]
+    w = dict(tw, nx=15, ny=15, nt=16)
+    src, p0, p1 = bench.make_inputs(w)
+    ref, z0, z1 = synth.random_source(15, 15, 16, seed=2)
+    assert np.array_equal(src[0], ref) and not p0.any() and not p1.any()
+    one = bench.make_inputs(bench.WORKLOADS["wave1d_63x64"])
+    many = bench.make_inputs(dict(bench.WORKLOADS["batch256_wave1d_63x64"], batch=3))
+    assert np.array_equal(many[0][0], one[0][0]) and not np.array_equal(many[0][1], many[0][0])
+    for a, b in zip(many[1:], one[1:]):
+        assert np.array_equal(a[0], b[0])
