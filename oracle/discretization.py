@@ -114,10 +114,11 @@ def dst_space(v: np.ndarray, g: Grid) -> np.ndarray:
     Section 2.3, to every time level of ``v`` (shape [..., nt] + level_shape).
 
     S is real, symmetric and orthogonal, so it is its own inverse.  This calls the
-    scipy.fft DST-I routine, a library primitive.
+    scipy.fft DST-I routine, a library primitive (on every host core: the threads
+    split the batch of transforms, so the result does not depend on their number).
     """
     axes = (-2, -1) if g.ny else (-1,)
-    return sfft.dstn(v, type=1, axes=axes, norm="ortho")
+    return sfft.dstn(v, type=1, axes=axes, norm="ortho", workers=-1)
 
 
 def dst_matrix(n: int) -> np.ndarray:

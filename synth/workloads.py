@@ -8,6 +8,7 @@ interior points x_i = i/(nx+1).
 from __future__ import annotations
 
 import numpy as np
+import scipy.fft as sfft
 
 
 def grid_points(nx: int, ny: int = 0):
@@ -68,7 +69,7 @@ def gaussian_field_source(nx: int, ny: int, nt: int, T: float = 1.0, ell: float 
     shape = (nt, ny, nx) if ny else (nt, nx)
     white = np.random.default_rng(seed).standard_normal(shape)
     spacings = [T / nt] + ([1.0 / (ny + 1)] if ny else []) + [1.0 / (nx + 1)]
-    spec = np.fft.rfftn(white)
+    spec = sfft.rfftn(white, workers=-1)
     del white
     k2 = None
     for ax, (n, d) in enumerate(zip(shape, spacings)):
@@ -76,7 +77,7 @@ def gaussian_field_source(nx: int, ny: int, nt: int, T: float = 1.0, ell: float 
         kk = (k ** 2).reshape([-1 if a == ax else 1 for a in range(len(shape))])
         k2 = kk if k2 is None else k2 + kk
     spec *= np.exp(-2.0 * np.pi ** 2 * ell ** 2 * k2)
-    field = np.fft.irfftn(spec, s=shape, axes=tuple(range(len(shape))))
+    field = sfft.irfftn(spec, s=shape, axes=tuple(range(len(shape))), workers=-1)
     del spec
     field /= np.sqrt(np.mean(field ** 2))
     z = np.zeros(shape[1:])
