@@ -87,6 +87,17 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
  * ABAC_TUNE_FILE names an optional cache file).  wg must hold 6 ints. */
 abac_status abac_plan_tiles(abac_plan *plan, int *wg);
 
+/* Override the tiles the tuner chose for the plan's first x-DST pass (wg_x), y-DST pass
+ * (wg_y, 2D only) and time pass (wg_t), in threads per workgroup; 0 keeps the current
+ * choice.  These passes carry no reduction: every sequence of the fast transforms of
+ * Section 2.3 is computed by the same arithmetic whatever the tile, so every legal tile
+ * gives bitwise the same results, and this call lets a caller (a test) run each one.
+ * ABAC_EINVAL (nothing changed) if a tile is not legal for its kernel (it must be a
+ * multiple of 64 and of the threads per sequence, and its LDS must fit the device), if
+ * the plan uses the fused x-y passes and wg_x or wg_y is nonzero, for ABAC_PREC_NONE, or
+ * while a solve is in progress.  Synchronises the plan stream. */
+abac_status abac_plan_set_tiles(abac_plan *plan, int wg_x, int wg_y, int wg_t);
+
 /* Release the plan (synchronises its stream; frees library-owned memory only). */
 abac_status abac_plan_destroy(abac_plan *plan);
 

@@ -27,7 +27,7 @@ EXPORTED = [
     "abac_status_string", "abac_last_error", "abac_fill_normal", "abac_server_create", "abac_server_destroy",
     "abac_server_submit", "abac_server_step", "abac_server_result", "abac_server_clock",
     "abac_server_bytes_in_use", "abac_plan_tiles", "abac_plan_set_coefficient", "abac_apply_T", "abac_apply_Cinv",
-    "abac_gmres_solve",
+    "abac_gmres_solve", "abac_plan_set_tiles",
 ]
 
 _lib = None
@@ -106,6 +106,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abac_gmres_solve.restype = I
     lib.abac_plan_set_coefficient.argtypes = [P, VP, VP, D]
     lib.abac_plan_set_coefficient.restype = I
+    lib.abac_plan_set_tiles.argtypes = [P, I, I, I]
+    lib.abac_plan_set_tiles.restype = I
     lib.abac_server_bytes_in_use.argtypes = [P]
     lib.abac_server_bytes_in_use.restype = SZ
     _lib = lib
@@ -293,6 +295,12 @@ class Plan:
         _check(self._lib.abac_plan_tiles(self._h, wg), "abac_plan_tiles")
         return {"dstx_fwd": wg[0], "dsty": wg[1], "time": wg[2], "dstx_inv": wg[3], "slab": wg[4],
                 "small": wg[5]}
+
+    def set_tiles(self, dstx_fwd: int = 0, dsty: int = 0, time: int = 0):
+        """Override the tuned tiles of the first x pass, the y pass and the time pass
+        (threads per workgroup; 0 keeps the current one).  Raises AbacError(EINVAL)
+        for a tile that is not legal for its kernel."""
+        _check(self._lib.abac_plan_set_tiles(self._h, int(dstx_fwd), int(dsty), int(time)), "abac_plan_set_tiles")
 
     # -- kernel timing -----------------------------------------------------------
     def profile(self, on: bool = True):

@@ -1027,6 +1027,35 @@ abac_status abac_profile_reset(abac_plan* p) {
   return ABAC_OK;
 }
 
+abac_status abac_plan_set_tiles(abac_plan* p, int wg_x, int wg_y, int wg_t) {
+  g_last_error.clear();
+  if (!p) return fail(ABAC_EINVAL, "plan is NULL");
+  if (p->active) return fail(ABAC_EINVAL, "a solve is in progress on this plan");
+  if (p->prec == ABAC_PREC_NONE) return fail(ABAC_EINVAL, "the plan has no transform passes");
+  DevPlan& P = p->P;
+  int dev = 0, maxlds = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  if ((wg_x || wg_y) && P.wg_s) return fail(ABAC_EINVAL, "the plan uses the fused x-y passes");
+  if (wg_y && !P.ny) return fail(ABAC_EINVAL, "a 1D plan has no y pass");
+  if (wg_x && !tile_fits(TK_XFWD, 2 * P.Mx, wg_x, p->prec, maxlds))
+    return fail(ABAC_EINVAL, "x-DST tile " + std::to_string(wg_x) + " is not legal for this plan");
+  if (wg_y && !tile_fits(TK_Y, 2 * P.My, wg_y, p->prec, maxlds))
+    return fail(ABAC_EINVAL, "y-DST tile " + std::to_string(wg_y) + " is not legal for this plan");
+  if (wg_t && !tile_fits(TK_TIME, P.nt, wg_t, p->prec, maxlds))
+    return fail(ABAC_EINVAL, "time tile " + std::to_string(wg_t) + " is not legal for this plan");
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (wg_x) P.wg_x = wg_x;
+  if (wg_y) P.wg_y = wg_y;
+  if (wg_t) P.wg_t = wg_t;
+  // kernels take the plan by value: a captured iteration holds the old tiles
+  if (p->iter_graph) {
+    HIP_TRY(hipGraphExecDestroy(p->iter_graph));
+    p->iter_graph = nullptr;
+  }
+  return ABAC_OK;
+}
+
 abac_status abac_plan_tiles(abac_plan* p, int* wg) {
   if (!p || !wg) return fail(ABAC_EINVAL, "NULL argument");
   wg[0] = p->P.wg_x;
