@@ -148,6 +148,26 @@ abac_status abac_apply_Cinv(abac_plan *plan, const double *r, double *z);
  * factor uses (C^{-1/2})^T = Y C^{-1/2} Y).  z may alias r. */
 abac_status abac_apply_Pinv(abac_plan *plan, const double *r, double *z);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): z = P_alpha^{-1} r as abac_apply_Pinv
+ * computes it, for `batch` right-hand sides of the grid (nx, ny, nt) with final time T,
+ * alpha and transform precision prec (ABAC_PREC_FP64 or ABAC_PREC_FP32), without a
+ * plan.  It calls no hipMalloc, hipFree or other allocating routine: the spectral
+ * tables (computed on the device) and the transform scratch live in a fixed device
+ * array of 128 MiB inside the library, one per GPU, held until the process ends.
+ *   r, z:    caller-owned DEVICE vectors [batch][nt][...], FP64; z may alias r.
+ *   stream:  hipStream_t (NULL = default stream); the call is asynchronous on it.
+ * Sizes, tiles and results follow abac_apply_Pinv's rules (the tuned tiles of a plan are
+ * replaced by the tuner's default tiles; the passes carry no reduction, so the result
+ * is the same).  ABAC_EINVAL if the tables plus batch * nt * (nx+1) * max(ny,1)
+ * transform values (8 bytes each in FP64, 4 in FP32) exceed 128 MiB, if alpha is not
+ * in (0, 0.5] (near 1 C_alpha can be singular; a plan checks that), or for
+ * ABAC_PREC_NONE.  Every call on one GPU uses that GPU's single array: calls that
+ * overlap on one GPU (different streams or threads without ordering) race and give
+ * wrong results; calls ordered on one stream are safe. */
+abac_status abac_apply_Pinv_noalloc(int nx, int ny, int nt, double T, double alpha, int prec, int batch,
+                                    const double *r, double *z, void *stream);
+
 /* Solve Y T u = Y f for every right-hand side in the batch by preconditioned MINRES
  * with zero initial guess (Section 3).  Stops a right-hand side at the first
  * iteration whose residual ||Y f - Y T u||_2 <= tol ||Y f||_2 (tracked by the MINRES

@@ -27,7 +27,7 @@ EXPORTED = [
     "abac_status_string", "abac_last_error", "abac_fill_normal", "abac_server_create", "abac_server_destroy",
     "abac_server_submit", "abac_server_step", "abac_server_result", "abac_server_clock",
     "abac_server_bytes_in_use", "abac_plan_tiles", "abac_plan_set_coefficient", "abac_apply_T", "abac_apply_Cinv",
-    "abac_gmres_solve", "abac_plan_set_tiles",
+    "abac_gmres_solve", "abac_plan_set_tiles", "abac_apply_Pinv_noalloc",
 ]
 
 _lib = None
@@ -106,6 +106,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abac_gmres_solve.restype = I
     lib.abac_plan_set_coefficient.argtypes = [P, VP, VP, D]
     lib.abac_plan_set_coefficient.restype = I
+    lib.abac_apply_Pinv_noalloc.argtypes = [I, I, I, D, D, I, I, VP, VP, VP]
+    lib.abac_apply_Pinv_noalloc.restype = I
     lib.abac_plan_set_tiles.argtypes = [P, I, I, I]
     lib.abac_plan_set_tiles.restype = I
     lib.abac_server_bytes_in_use.argtypes = [P]
@@ -130,6 +132,25 @@ def fill_normal(out: torch.Tensor, seed: int, stream=None):
     _check(load_library().abac_fill_normal(ctypes.c_void_p(s.cuda_stream), ctypes.c_void_p(out.data_ptr()),
                                            out.numel(), seed), "abac_fill_normal")
     return out
+
+
+def apply_Pinv_noalloc(r: torch.Tensor, nx: int, ny: int, nt: int, T: float = 1.0, alpha: float = 1e-3,
+                       prec: str = "fp64", z: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """z = P_alpha^{-1} r without a plan and without any device allocation by the
+    library (abac_apply_Pinv_noalloc).  r: contiguous float64 GPU tensor [batch][nt][...]."""
+    per = nt * nx * (ny if ny else 1)
+    if r.device.type != "cuda" or r.dtype != torch.float64 or not r.is_contiguous() or r.numel() % per:
+        raise TypeError(f"r must be a contiguous float64 GPU tensor of batch x {per} values")
+    z = torch.empty_like(r) if z is None else z
+    if z.device != r.device or z.dtype != torch.float64 or not z.is_contiguous() or z.numel() != r.numel():
+        raise TypeError("z must be a contiguous float64 GPU tensor like r")
+    s = stream if stream is not None else torch.cuda.current_stream(r.device)
+    with torch.cuda.device(r.device):
+        _check(load_library().abac_apply_Pinv_noalloc(nx, ny, nt, float(T), float(alpha), PREC[prec],
+                                                      r.numel() // per, ctypes.c_void_p(r.data_ptr()),
+                                                      ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(s.cuda_stream)),
+               "abac_apply_Pinv_noalloc")
+    return z
 
 
 def workspace_bytes(nx: int, ny: int, nt: int, prec: str = "fp64", batch: int = 1) -> int:

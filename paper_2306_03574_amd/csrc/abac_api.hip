@@ -537,6 +537,110 @@ hipError_t upload_table(void* dst, const std::vector<double>& v, int prec, hipSt
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Plan-free, allocation-free P_alpha^{-1}: the spectral tables and the transform
+// scratch live in one file-scope device array.  Each GPU holds its own copy at its own
+// address; host code reaches it only through the address hipGetSymbolAddress returns
+// on that device (the array's name on the host is a stand-in, not a device address).
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kNoallocBytes = (size_t)128 << 20;
+__device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+// Address of this device's copy of `scratch`, looked up once per device with that
+// device current.
+abac_status noalloc_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(ABAC_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> g(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_noalloc_ptr[dev] = ptr;
+  }
+  *out = g_noalloc_ptr[dev];
+  return ABAC_OK;
+}
+
+struct NoallocLayout {
+  size_t twx, twy, twt, beta, abk, sc, sci, scr, total;
+};
+
+NoallocLayout noalloc_layout(const DevPlan& P, int prec) {
+  NoallocLayout Lo{};
+  const size_t real = prec == ABAC_PREC_FP32 ? sizeof(float) : sizeof(double);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
+  Lo.twx = take(2 * real * 2 * P.Mx);
+  Lo.twy = take(2 * real * 2 * P.My);
+  Lo.twt = take(2 * real * P.nt);
+  Lo.beta = take(real * P.ms);
+  Lo.abk = take(2 * real * 2 * P.nt);
+  Lo.sc = take(real * P.nt);
+  Lo.sci = take(real * P.nt);
+  Lo.scr = take(real * (size_t)P.NS * P.B);
+  Lo.total = o;
+  return Lo;
+}
+
+// The tables of plan creation, computed on the device in FP64 and stored in the
+// transform precision: twiddles exp(-2 pi i e/L) of the x, y and time lengths; beta_q =
+// (tau^2/2) (kx + ky) of each scratch mode (1 in the pad column); (A_k, B_k) with
+// mu_k(beta) = A_k + beta B_k, A_k = (1 - a w_k)^2 evaluated without cancellation as
+// ((1-a) + 2a sin^2(th/2)) + i a sin th, B_k = 1 + a^2 w_k^2; and a^{+-t}.
+template <typename T>
+__global__ void k_noalloc_tables(DevPlan P, double la, double a, double oma) {
+  using C = cplx<T>;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < 2 * P.Mx) {
+    double sn, cs;
+    sincospi(2.0 * e / (2.0 * P.Mx), &sn, &cs);
+    reinterpret_cast<C*>(const_cast<void*>(P.twx))[e] = C{(T)cs, (T)-sn};
+  }
+  if (e < 2 * P.My) {
+    double sn, cs;
+    sincospi(2.0 * e / (2.0 * P.My), &sn, &cs);
+    reinterpret_cast<C*>(const_cast<void*>(P.twy))[e] = C{(T)cs, (T)-sn};
+  }
+  if (e < P.nt) {
+    double sn, cs;
+    sincospi(2.0 * e / P.nt, &sn, &cs);
+    reinterpret_cast<C*>(const_cast<void*>(P.twt))[e] = C{(T)cs, (T)-sn};
+    const double sh = sinpi((double)e / P.nt);
+    const double re = oma + 2.0 * a * sh * sh, im = a * sinpi(2.0 * e / P.nt);
+    double s2, c2;
+    sincospi(4.0 * e / P.nt, &s2, &c2);
+    C* abk = reinterpret_cast<C*>(const_cast<void*>(P.abk));
+    abk[2 * e] = C{(T)(re * re - im * im), (T)(2.0 * re * im)};
+    abk[2 * e + 1] = C{(T)(1.0 + a * a * c2), (T)(-a * a * s2)};
+    reinterpret_cast<T*>(const_cast<void*>(P.sc))[e] = (T)exp(la * e);
+    reinterpret_cast<T*>(const_cast<void*>(P.sci))[e] = (T)exp(-la * e);
+  }
+  if (e < P.ms) {
+    const int yy = e / P.Mx, xx = e - yy * P.Mx;
+    double b = 1.0;
+    if (xx < P.nx) {
+      const double hx = 1.0 / P.Mx;
+      const double sx = sinpi((xx + 1) * hx * 0.5);
+      double k = 4.0 / (hx * hx) * sx * sx;
+      if (P.ny) {
+        const double hy = 1.0 / P.My;
+        const double sy = sinpi((yy + 1) * hy * 0.5);
+        k += 4.0 / (hy * hy) * sy * sy;
+      }
+      b = 0.5 * P.tau2 * k;
+    }
+    reinterpret_cast<T*>(const_cast<void*>(P.beta))[e] = (T)b;
+  }
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t abac_workspace_bytes(int nx, int ny, int nt, int prec, int batch) {
@@ -1064,6 +1168,75 @@ abac_status abac_plan_tiles(abac_plan* p, int* wg) {
   wg[3] = p->P.wg_xi;
   wg[4] = p->P.wg_s;
   wg[5] = p->P.small ? 512 : 0;
+  return ABAC_OK;
+}
+
+abac_status abac_apply_Pinv_noalloc(int nx, int ny, int nt, double T, double alpha, int prec, int batch,
+                                    const double* r, double* z, void* stream) {
+  g_last_error.clear();
+  if (!r || !z) return fail(ABAC_EINVAL, "NULL argument");
+  if (prec != ABAC_PREC_FP64 && prec != ABAC_PREC_FP32)
+    return fail(ABAC_EINVAL, "prec must be 0 (FP64) or 1 (FP32) transforms");
+  if (!(alpha > 0) || !(alpha <= 0.5))
+    return fail(ABAC_EINVAL, "alpha must be in (0, 0.5] (near 1 C_alpha may be singular: use a plan)");
+  DevPlan P;
+  abac_status s = describe(nx, ny, nt, T, alpha, prec, batch, P);
+  if (s != ABAC_OK) return s;
+  const NoallocLayout Lo = noalloc_layout(P, prec);
+  if (Lo.total > kNoallocBytes)
+    return fail(ABAC_EINVAL, "problem needs " + std::to_string(Lo.total) + " bytes of scratch; the allocation-free "
+                             "entry point holds at most " + std::to_string(kNoallocBytes) +
+                             " (use a plan with a workspace)");
+  int dev = 0, maxlds = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  void* base_v = nullptr;
+  s = noalloc_scratch(dev, &base_v);
+  if (s != ABAC_OK) return s;
+  // the fixed tile rules of plan creation, without timing (no tuner: it would write
+  // trial launches into the shared scratch and synchronise the stream)
+  P.wg_x = default_wg(TK_XFWD, 2 * P.Mx, prec, maxlds);
+  P.wg_xi = 0;
+  for (int wg : kTileCandidates)
+    if (!P.wg_xi && tile_fits(TK_XINV, 2 * P.Mx, wg, prec, maxlds)) P.wg_xi = wg;
+  P.wg_y = ny ? default_wg(TK_Y, 2 * P.My, prec, maxlds) : 256;
+  P.wg_t = default_wg(TK_TIME, nt, prec, maxlds);
+  P.wg_s = slab_wg(nx, ny, prec, maxlds, 8192);
+  if (!P.wg_x || !P.wg_xi || !P.wg_y || !P.wg_t)
+    return fail(ABAC_EINVAL, "transform does not fit the device LDS; use the FP32 transforms for this size");
+  char* base = static_cast<char*>(base_v);
+  P.twx = base + Lo.twx;
+  P.twy = base + Lo.twy;
+  P.twt = base + Lo.twt;
+  P.beta = base + Lo.beta;
+  P.abk = base + Lo.abk;
+  P.sc = base + Lo.sc;
+  P.sci = base + Lo.sci;
+  P.scratch = base + Lo.scr;
+  // every scratch value an apply reads is written earlier in the same apply (the first
+  // pass writes whole rows, the zero pad column included), so nothing is cleared
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const double la = std::log(alpha) / nt;
+  const int n = std::max(std::max(2 * P.Mx, 2 * P.My), std::max(nt, P.ms));
+  if (prec == ABAC_PREC_FP32)
+    hipLaunchKernelGGL(k_noalloc_tables<float>, dim3((n + 255) / 256), dim3(256), 0, st, P, la, std::exp(la),
+                       -std::expm1(la));
+  else
+    hipLaunchKernelGGL(k_noalloc_tables<double>, dim3((n + 255) / 256), dim3(256), 0, st, P, la, std::exp(la),
+                       -std::expm1(la));
+  HIP_TRY(hipGetLastError());
+  hipError_t e;
+  if (P.wg_s) {
+    if ((e = launch_dst2_fwd(P, prec, FWD_PLAIN, 0, r, st)) != hipSuccess) return hip_fail(e, "launch_dst2_fwd");
+    if ((e = launch_time(P, prec, 0, st)) != hipSuccess) return hip_fail(e, "launch_time");
+    if ((e = launch_dst2_inv(P, prec, INV_PLAIN, z, st)) != hipSuccess) return hip_fail(e, "launch_dst2_inv");
+  } else {
+    if ((e = launch_dstx_fwd(P, prec, FWD_PLAIN, 0, r, st)) != hipSuccess) return hip_fail(e, "launch_dstx_fwd");
+    if (P.ny && (e = launch_dsty(P, prec, 0, st)) != hipSuccess) return hip_fail(e, "launch_dsty");
+    if ((e = launch_time(P, prec, 0, st)) != hipSuccess) return hip_fail(e, "launch_time");
+    if (P.ny && (e = launch_dsty(P, prec, 0, st)) != hipSuccess) return hip_fail(e, "launch_dsty");
+    if ((e = launch_dstx_inv(P, prec, INV_PLAIN, z, st)) != hipSuccess) return hip_fail(e, "launch_dstx_inv");
+  }
   return ABAC_OK;
 }
 

@@ -75,3 +75,19 @@ def test_status_strings(lib):
     assert lib.abac_status_string(0) == b"ok"
     assert lib.abac_status_string(-4) == b"not converged"
     assert lib.abac_status_string(-5) == b"breakdown"
+
+
+@pytest.mark.parametrize("args", [
+    (511, 511, 512, 1.0, 1e-3, 1, 1),   # 511^2 x 512 FP32 scratch: over the fixed array
+    (255, 255, 256, 1.0, 1e-3, 0, 2),   # two FP64 right-hand sides of 255^2 x 256: over it
+    (63, 0, 64, 1.0, 0.9, 0, 1),        # alpha near 1 (singularity check needs a plan)
+    (63, 0, 64, 1.0, 1e-3, 2, 1),       # no transforms to apply
+    (62, 0, 64, 1.0, 1e-3, 0, 1),       # nx+1 not a power of two
+])
+def test_noalloc_apply_rejects_without_touching_the_gpu(lib, args):
+    """The allocation-free P^{-1} checks sizes and arguments on the host first; the
+    pointers are never dereferenced on these paths."""
+    dummy = ctypes.c_void_p(256)
+    st = lib.abac_apply_Pinv_noalloc(*args, dummy, dummy, None)
+    assert st == -1
+    assert len(lib.abac_last_error()) > 0
