@@ -262,6 +262,6 @@ enum TransformKind : int { TK_XFWD = 0, TK_XINV = 1, TK_Y = 2, TK_TIME = 3 };
 // dynamic LDS bytes of one workgroup (0 if the tile is not legal)
 size_t transform_lds_bytes(int kind, int L, int wg, int prec);
 bool transform_tile_valid(int kind, int L, int wg, int prec);
-int transform_tps(int L);
+int transform_tps(int L, int prec);   // threads per sequence of length L (prec 1: FP32)
 
 }  // namespace abac

@@ -120,9 +120,9 @@ template <int R, bool INV, typename C> __device__ __forceinline__ void dftR(C* u
 
 // Factorisation of each supported length: outer radix R (first and last pass) and
 // up to two middle radices (0 = absent).  Middle radices divide R.
-template <int L> struct FftShape;
+template <int L> struct FftShapeDefault;
 #define ABAC_FFT_SHAPE(LL, RR, M1, M2) \
-  template <> struct FftShape<LL> { static constexpr int R = RR, m1 = M1, m2 = M2; \
+  template <> struct FftShapeDefault<LL> { static constexpr int R = RR, m1 = M1, m2 = M2; \
     static constexpr int passes = (LL == RR) ? 1 : 2 + (M1 ? 1 : 0) + (M2 ? 1 : 0); };
 ABAC_FFT_SHAPE(4, 4, 0, 0)
 ABAC_FFT_SHAPE(8, 8, 0, 0)
@@ -138,7 +138,19 @@ ABAC_FFT_SHAPE(4096, 16, 16, 0)
 ABAC_FFT_SHAPE(8192, 16, 2, 16)
 #undef ABAC_FFT_SHAPE
 
-template <int L> constexpr int fft_tps() { return L / FftShape<L>::R; }
+// The factorisation per precision.  FP64 values take twice the registers of FP32 ones,
+// so FP64 passes favour radix 8 (more threads per sequence, higher occupancy) and FP32
+// passes radix 16 (fewer exchanges through LDS): 512 = 16 x 2 x 16 in FP32 and
+// 1024 = 8 x 4 x 4 x 8 in FP64 differ from the shared table.
+template <typename T, int L> struct FftShape : FftShapeDefault<L> {};
+template <> struct FftShape<float, 512> {
+  static constexpr int R = 16, m1 = 2, m2 = 0, passes = 3;
+};
+template <> struct FftShape<double, 1024> {
+  static constexpr int R = 8, m1 = 4, m2 = 4, passes = 4;
+};
+
+template <typename T, int L> constexpr int fft_tps() { return L / FftShape<T, L>::R; }
 
 // One Stockham (decimation in time, autosort) pass of radix r over a length-L
 // sequence, for the butterflies owned by this thread.  Butterfly b reads elements
@@ -173,7 +185,7 @@ __device__ __forceinline__ int stockham_dst(int b, int Ns, int i) {
 template <typename T, int L, bool INV, bool FROM_LDS = false>
 __device__ __forceinline__ void fft_seq(cplx<T>* v, int j, cplx<T>* lds, int S, const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
-  using Sh = FftShape<L>;
+  using Sh = FftShape<T, L>;
   constexpr int R = Sh::R;
   constexpr int TPS = L / R;
   if constexpr (FROM_LDS) {

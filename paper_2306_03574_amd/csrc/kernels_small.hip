@@ -111,7 +111,7 @@ __device__ __noinline__ void iter_small(const DevPlan& P, const double* __restri
   // Lanczos vector and z_{j+1} = P^{-1} q: x-DST (Lanczos fused), time pass, inverse
   // x-DST with <q, p>, then gamma_{j+1} and the Givens step
   if (st->state == ST_RUNNING) {
-    constexpr int SX = seqs_of<L, WG>(), ST = seqs_of<NT, WG>();
+    constexpr int SX = seqs_of<T, L, WG>(), ST = seqs_of<T, NT, WG>();
     const int xtiles = (P.nt + 2 * SX - 1) / (2 * SX);
     const int ttiles = (P.ms / 2 + ST - 1) / ST;
     for (int t = 0; t < xtiles; ++t) {
@@ -185,7 +185,7 @@ __device__ __noinline__ void setup_small(const DevPlan& P, const double* __restr
   }
   double tot = 0.0;
   if (st->state == ST_RUNNING) {
-    constexpr int SX = seqs_of<L, WG>(), ST = seqs_of<NT, WG>();
+    constexpr int SX = seqs_of<T, L, WG>(), ST = seqs_of<T, NT, WG>();
     const int xtiles = (P.nt + 2 * SX - 1) / (2 * SX);
     const int ttiles = (P.ms / 2 + ST - 1) / ST;
     for (int t = 0; t < xtiles; ++t) {

@@ -78,12 +78,12 @@ constexpr size_t slab_bytes() {
 
 template <typename T, int L, int WG>
 constexpr size_t slab_lds_of() {
-  return slab_bytes<T, L>() + (size_t)seqs_of<L, WG>() * L * sizeof(cplx<T>);
+  return slab_bytes<T, L>() + (size_t)seqs_of<T, L, WG>() * L * sizeof(cplx<T>);
 }
 
 template <typename T, int L, int WG>
 constexpr bool slab_ok() {
-  return L >= 16 && L <= 256 && WG >= fft_tps<L>() && WG % fft_tps<L>() == 0 && WG % 64 == 0 &&
+  return L >= 16 && L <= 256 && WG >= fft_tps<T, L>() && WG % fft_tps<T, L>() == 0 && WG % 64 == 0 &&
          slab_lds_of<T, L, WG>() <= kMaxTransformLds;
 }
 
@@ -96,7 +96,7 @@ constexpr bool slab_ok() {
 template <typename T, int L, int WG, bool ROWS>
 __device__ __forceinline__ void slab_dst(T* slab, int nlines, cplx<T>* exch, const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
-  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_of<L, WG>(), M = L / 2, LD = M + 1;
+  constexpr int R = FftShape<T, L>::R, TPS = L / R, S = seqs_of<T, L, WG>(), M = L / 2, LD = M + 1;
   const int s = threadIdx.x % S, j = threadIdx.x / S;
   const int npairs = (nlines + 1) / 2;
   const T scl = (T)(1.0 / sqrt((double)L));
@@ -288,7 +288,7 @@ hipError_t launch_x_fwd_t(const DevPlan& P, int mode, int check, const double* i
   if constexpr (!tile_ok<T, L, WG, TK_XFWD>()) {
     return hipErrorInvalidValue;
   } else {
-    constexpr int S = seqs_of<L, WG>();
+    constexpr int S = seqs_of<T, L, WG>();
     const int rows = P.nt * P.ny1;
     dim3 grid((rows + 2 * S - 1) / (2 * S), P.B);
     const size_t lds = lds_of<T, L, WG, TK_XFWD>();
@@ -302,7 +302,7 @@ hipError_t launch_x_inv_t(const DevPlan& P, int mode, double* out, hipStream_t s
   if constexpr (!tile_ok<T, L, WG, TK_XINV>()) {
     return hipErrorInvalidValue;
   } else {
-    constexpr int S = seqs_of<L, WG>();
+    constexpr int S = seqs_of<T, L, WG>();
     const int rows = P.nt * P.ny1;
     dim3 grid((rows + 2 * S - 1) / (2 * S), P.B);
     const size_t lds = lds_of<T, L, WG, TK_XINV>();
@@ -316,7 +316,7 @@ hipError_t launch_y_t(const DevPlan& P, int check, hipStream_t s) {
   if constexpr (!tile_ok<T, L, WG, TK_Y>()) {
     return hipErrorInvalidValue;
   } else {
-    constexpr int S = seqs_of<L, WG>();
+    constexpr int S = seqs_of<T, L, WG>();
     const int cpairs = P.Mx / 2;
     const int bpl = (cpairs + S - 1) / S;
     dim3 grid(bpl * P.nt, P.B);
@@ -331,7 +331,7 @@ hipError_t launch_time_t(const DevPlan& P, int check, int inv1, hipStream_t s) {
   if constexpr (!tile_ok<T, NT, WG, TK_TIME>()) {
     return hipErrorInvalidValue;
   } else {
-    constexpr int S = seqs_of<NT, WG>();
+    constexpr int S = seqs_of<T, NT, WG>();
     const int npairs = P.ms / 2;
     dim3 grid((npairs + S - 1) / S, P.B);
     const size_t lds = lds_of<T, NT, WG, TK_TIME>();
@@ -503,7 +503,7 @@ hipError_t launch_dst2_inv(const DevPlan& P, int prec, int mode, double* out, hi
 int slab_wg(int nx, int ny, int prec, int maxlds, size_t margin) {
   if (!ny || nx != ny) return 0;
   const int L = 2 * (nx + 1);
-  const int tps = transform_tps(L);
+  const int tps = transform_tps(L, prec);
   if (!tps) return 0;
   for (int wg : {512, 256, 128, 64}) {
     if (wg / tps > std::max((nx + 1) / 2, 64 / tps)) continue;
@@ -517,25 +517,27 @@ bool transform_tile_valid(int kind, int L, int wg, int prec) {
   return (prec ? tile_check_k<float>(kind, L, wg) : tile_check_k<double>(kind, L, wg)) == hipSuccess;
 }
 
-int transform_tps(int L) {
+template <typename T> int transform_tps_t(int L) {
   switch (L) {
-    case 8: return fft_tps<8>();
-    case 16: return fft_tps<16>();
-    case 32: return fft_tps<32>();
-    case 64: return fft_tps<64>();
-    case 128: return fft_tps<128>();
-    case 256: return fft_tps<256>();
-    case 512: return fft_tps<512>();
-    case 1024: return fft_tps<1024>();
-    case 2048: return fft_tps<2048>();
-    case 4096: return fft_tps<4096>();
-    case 8192: return fft_tps<8192>();
+    case 8: return fft_tps<T, 8>();
+    case 16: return fft_tps<T, 16>();
+    case 32: return fft_tps<T, 32>();
+    case 64: return fft_tps<T, 64>();
+    case 128: return fft_tps<T, 128>();
+    case 256: return fft_tps<T, 256>();
+    case 512: return fft_tps<T, 512>();
+    case 1024: return fft_tps<T, 1024>();
+    case 2048: return fft_tps<T, 2048>();
+    case 4096: return fft_tps<T, 4096>();
+    case 8192: return fft_tps<T, 8192>();
     default: return 0;
   }
 }
 
+int transform_tps(int L, int prec) { return prec == 1 ? transform_tps_t<float>(L) : transform_tps_t<double>(L); }
+
 int dstx_blocks(const DevPlan& P, int wg) {
-  const int S = wg / transform_tps(2 * P.Mx);
+  const int S = wg / transform_tps(2 * P.Mx, P.prec);
   const int rows = P.nt * P.ny1;
   return (rows + 2 * S - 1) / (2 * S);
 }

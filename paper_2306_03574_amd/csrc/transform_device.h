@@ -10,7 +10,7 @@
 namespace abac {
 namespace {
 
-template <int L, int WG> constexpr int seqs_of() { return WG / fft_tps<L>(); }
+template <typename T, int L, int WG> constexpr int seqs_of() { return WG / fft_tps<T, L>(); }
 
 // LDS bytes of one workgroup: the interleaved sequences; the inverse x pass reuses
 // the region for its FP64 output staging; the y pass (length <= 1024) also holds its
@@ -19,9 +19,9 @@ template <int L, int WG> constexpr int seqs_of() { return WG / fft_tps<L>(); }
 template <typename T, int L, int WG, int KIND>
 constexpr size_t lds_of() {
   constexpr size_t c = sizeof(cplx<T>);
-  constexpr size_t data = (size_t)seqs_of<L, WG>() * L * c;
+  constexpr size_t data = (size_t)seqs_of<T, L, WG>() * L * c;
   if constexpr (KIND == TK_XINV) {
-    constexpr size_t ostage = (size_t)2 * seqs_of<L, WG>() * (L / 2 + 1) * sizeof(double);
+    constexpr size_t ostage = (size_t)2 * seqs_of<T, L, WG>() * (L / 2 + 1) * sizeof(double);
     return data > ostage ? data : ostage;
   } else if constexpr (KIND == TK_Y) {
     return data + (size_t)L * c;
@@ -34,7 +34,7 @@ constexpr size_t lds_of() {
 
 template <typename T, int L, int WG, int KIND>
 constexpr bool tile_ok() {
-  return WG >= fft_tps<L>() && WG % fft_tps<L>() == 0 && WG % 64 == 0 && lds_of<T, L, WG, KIND>() <= kMaxTransformLds;
+  return WG >= fft_tps<T, L>() && WG % fft_tps<T, L>() == 0 && WG % 64 == 0 && lds_of<T, L, WG, KIND>() <= kMaxTransformLds;
 }
 
 // Copy an n-entry table into LDS (the caller places the barrier).
@@ -43,6 +43,15 @@ __device__ __forceinline__ void stage_table(V* dst, const V* __restrict__ src, i
   for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
 }
 
+// Reciprocal square root, absolute value and sign transfer in the working precision
+// (the FP32 path must not round-trip through the FP64 routines).
+__device__ __forceinline__ float rsqrt_w(float v) { return rsqrtf(v); }
+__device__ __forceinline__ double rsqrt_w(double v) { return rsqrt(v); }
+__device__ __forceinline__ float fabs_w(float v) { return fabsf(v); }
+__device__ __forceinline__ double fabs_w(double v) { return fabs(v); }
+__device__ __forceinline__ float copysign_w(float a, float b) { return copysignf(a, b); }
+__device__ __forceinline__ double copysign_w(double a, double b) { return copysign(a, b); }
+
 template <typename T>
 __device__ __forceinline__ cplx<T> inv_sqrt_principal(cplx<T> mu) {
   // 1/s(mu), s the principal square root.  With |mu| = sqrt(x^2 + y^2) and
@@ -50,17 +59,17 @@ __device__ __forceinline__ cplx<T> inv_sqrt_principal(cplx<T> mu) {
   // for x < 0, and 1/s = conj(s)/|mu|.  Two reciprocal square roots, no division.
   const T x = mu.x, y = mu.y;
   const T rr = x * x + y * y;
-  const T g = rsqrt(rr);                 // 1/|mu|
-  const T w2 = (rr * g + fabs(x)) * (T)0.5;
-  const T h = rsqrt(w2);                 // 1/w
+  const T g = rsqrt_w(rr);               // 1/|mu|
+  const T w2 = (rr * g + fabs_w(x)) * (T)0.5;
+  const T h = rsqrt_w(w2);               // 1/w
   const T w = w2 * h;
   T sr, si;
   if (x >= (T)0) {
     sr = w;
     si = (T)0.5 * y * h;
   } else {
-    sr = (T)0.5 * fabs(y) * h;
-    si = copysign(w, y);
+    sr = (T)0.5 * fabs_w(y) * h;
+    si = copysign_w(w, y);
   }
   return cplx<T>{sr * g, -si * g};
 }
@@ -108,7 +117,7 @@ template <typename T, int L, int WG>
 __device__ __forceinline__ void dstx_fwd_tile(const DevPlan& P, int mode, const double* __restrict__ in, int b,
                                               int tile, const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
-  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_of<L, WG>(), Mx = L / 2;
+  constexpr int R = FftShape<T, L>::R, TPS = L / R, S = seqs_of<T, L, WG>(), Mx = L / 2;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   T* stage = reinterpret_cast<T*>(smem);
@@ -212,7 +221,7 @@ __device__ __forceinline__ void dstx_fwd_tile(const DevPlan& P, int mode, const 
 template <typename T, int L, int WG>
 __device__ __forceinline__ void dsty_tile(const DevPlan& P, int b, int lbk) {
   using C = cplx<T>;
-  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_of<L, WG>(), My = L / 2;
+  constexpr int R = FftShape<T, L>::R, TPS = L / R, S = seqs_of<T, L, WG>(), My = L / 2;
   extern __shared__ __align__(16) unsigned char smem[];
   C* tws = reinterpret_cast<C*>(smem);
   C* lds = tws + L;
@@ -274,7 +283,7 @@ __device__ __forceinline__ cplx<T> inv_complex(cplx<T> mu) {
 
 template <typename T, int NT>
 struct SpectralWeights {
-  static constexpr int NU = FftShape<NT>::R / 2 + 1;   // frequency slots of one thread
+  static constexpr int NU = FftShape<T, NT>::R / 2 + 1;   // frequency slots of one thread
   cplx<T> sp[NU], sm[NU];
 };
 
@@ -282,20 +291,26 @@ struct SpectralWeights {
 // k = j + u TPS <= NT/2 this thread handles; they depend on the mode pair only, so both
 // passes of K Y K Y use the same ones.
 template <typename T, int NT>
+__device__ __forceinline__ void spectral_weight_slot(SpectralWeights<T, NT>& W, int u, int k, const cplx<T>* abk, T ba,
+                                                     T bb, T scale, int inv1) {
+  using C = cplx<T>;
+  const C A = abk[2 * k], Bk = abk[2 * k + 1];
+  const C mua = C{A.x + ba * Bk.x, A.y + ba * Bk.y}, mub = C{A.x + bb * Bk.x, A.y + bb * Bk.y};
+  const C Ma = inv1 ? inv_complex<T>(mua) : inv_sqrt_principal<T>(mua);
+  const C Mb = inv1 ? inv_complex<T>(mub) : inv_sqrt_principal<T>(mub);
+  W.sp[u] = cscale(cadd(Ma, Mb), scale);
+  W.sm[u] = cscale(csub(Ma, Mb), scale);
+}
+
+template <typename T, int NT>
 __device__ __forceinline__ void spectral_weights(SpectralWeights<T, NT>& W, int j, const cplx<T>* abk, T ba, T bb,
                                                  T scale, int inv1) {
-  using C = cplx<T>;
-  constexpr int R = FftShape<NT>::R, TPS = NT / R;
+  constexpr int R = FftShape<T, NT>::R, TPS = NT / R;
+  // slots u < R/2 hold k = j + u TPS < nt/2; the last slot (k = nt/2) is applied only by
+  // thread 0 (spectral_apply), so only thread 0 evaluates it
 #pragma unroll
-  for (int u = 0; u < SpectralWeights<T, NT>::NU; ++u) {
-    const int k = min(j + u * TPS, NT / 2);   // out-of-range slots are never applied
-    const C A = abk[2 * k], Bk = abk[2 * k + 1];
-    const C mua = C{A.x + ba * Bk.x, A.y + ba * Bk.y}, mub = C{A.x + bb * Bk.x, A.y + bb * Bk.y};
-    const C Ma = inv1 ? inv_complex<T>(mua) : inv_sqrt_principal<T>(mua);
-    const C Mb = inv1 ? inv_complex<T>(mub) : inv_sqrt_principal<T>(mub);
-    W.sp[u] = cscale(cadd(Ma, Mb), scale);
-    W.sm[u] = cscale(csub(Ma, Mb), scale);
-  }
+  for (int u = 0; u < R / 2; ++u) spectral_weight_slot<T, NT>(W, u, j + u * TPS, abk, ba, bb, scale, inv1);
+  if (j == 0) spectral_weight_slot<T, NT>(W, R / 2, NT / 2, abk, ba, bb, scale, inv1);
 }
 
 // Apply the weights to the packed spectrum held in registers (v[i] = Z[j + i TPS]):
@@ -309,7 +324,7 @@ template <typename T, int NT>
 __device__ __forceinline__ void spectral_apply(cplx<T>* v, int j, cplx<T>* my, int S,
                                                const SpectralWeights<T, NT>& W) {
   using C = cplx<T>;
-  constexpr int R = FftShape<NT>::R, TPS = NT / R, H = R / 2;
+  constexpr int R = FftShape<T, NT>::R, TPS = NT / R, H = R / 2;
   if (j != 0) {
 #pragma unroll
     for (int i = H; i < R; ++i) my[(j + i * TPS) * S] = v[i];
@@ -348,7 +363,7 @@ __device__ __forceinline__ void spectral_apply(cplx<T>* v, int j, cplx<T>* my, i
 template <typename T, int NT, int WG>
 __device__ __forceinline__ void time_tile(const DevPlan& P, int inv1, int b, int lbk) {
   using C = cplx<T>;
-  constexpr int R = FftShape<NT>::R, TPS = NT / R, S = seqs_of<NT, WG>();
+  constexpr int R = FftShape<T, NT>::R, TPS = NT / R, S = seqs_of<T, NT, WG>();
   extern __shared__ __align__(16) unsigned char smem[];
   // LDS: twiddles [NT], (A_k, B_k) [2 NT], a^t [NT], a^-t [NT], then the sequences
   C* tws = reinterpret_cast<C*>(smem);
@@ -430,7 +445,7 @@ template <typename T, int L, int WG>
 __device__ __forceinline__ double dstx_inv_tile(const DevPlan& P, int mode, double* __restrict__ outp, int b,
                                                 int tile, const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
-  constexpr int R = FftShape<L>::R, TPS = L / R, S = seqs_of<L, WG>(), Mx = L / 2;
+  constexpr int R = FftShape<T, L>::R, TPS = L / R, S = seqs_of<T, L, WG>(), Mx = L / 2;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   T* stage = reinterpret_cast<T*>(smem);

@@ -32,8 +32,8 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 TOL = 1e-8
 # FP32-transform P_alpha^{-1} at 511^2 x 512 (alpha 1e-3): measured relative error
-# (max norm) times a small factor
-FP32_PINV_C3 = 50 * 6e-8 / 1e-3
+# (max norm) 1.3e-5, times 5
+FP32_PINV_C3 = 6.5e-5
 
 
 def _say(msg):

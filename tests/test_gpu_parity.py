@@ -77,7 +77,9 @@ def test_apply_Pinv_fp32(nx, ny, nt, alpha):
     p = _plan(nx, ny, nt, alpha=alpha, prec="fp32")
     z = _host(p.apply_Pinv(_dev(r[None])))[0]
     ref = pc.apply_Pinv(g, alpha, r)
-    assert _rel(z, ref) < 50 * 6e-8 / alpha
+    err = _rel(z, ref)
+    print(f"[obs] fp32 {nx}x{ny}x{nt} alpha={alpha} P^-1 rel.err {err:.3e}", flush=True)
+    assert err < 50 * 6e-8 / alpha
 
 
 def test_apply_Pinv_alpha_one_matches_dense():

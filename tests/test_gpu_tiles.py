@@ -86,7 +86,7 @@ def test_every_legal_tile_matches_oracle(kind, L, prec):
     Lm = L_matrix(g)
     ref_x = mr.minres(lambda u: aao.apply_A(g, u, Lm), lambda y: pc.apply_Pinv(g, ALPHA, y),
                       aao.reverse_time(f), fixed_iters=K_FIXED).x
-    zbound = 1e-10 if prec == "fp64" else 5e-4   # FP32: eps32 / alpha times a small factor
+    zbound = 1e-10 if prec == "fp64" else 7e-5   # FP32: measured 5e-6 .. 1.4e-5 (about eps32 / (5 alpha)), times 5
 
     def run():
         z = _host(p.apply_Pinv(_dev(r[None])))[0]
