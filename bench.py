@@ -80,7 +80,8 @@ def algorithmic_bytes(w, prec, iters_total, solves, fused=False):
                 8 N + s NS      iteration, plus the set-up pass (read b)
       dsty      2 s NS         (read + write scratch) per launch, 2 launches per apply
       time      2 s NS         (read + write scratch) per apply
-      dstx_inv  s NS + 16 N    (read scratch, write p, read q) per apply
+      dstx_inv  s NS + 8 N     (read scratch, write p) per apply; <q, p> comes from the
+                               time pass (the squared norm of its first factor's output)
       update    24 N           (read r, v; write r) per iteration while the Krylov basis
                                is resident (iterations 1..12), 72 N after it (also
                                read z, w1, w2, x; write w, x)
@@ -97,15 +98,15 @@ def algorithmic_bytes(w, prec, iters_total, solves, fused=False):
     s = 8 if prec == "fp64" else 4
     applies = iters_total + solves
     if fused:
-        per_iter = 16 * N + (32 * N + s * NS) + 2 * s * NS + (s * NS + 16 * N) + 24 * N
-        setup = 24 * N + (8 * N + s * NS) + 2 * s * NS + (s * NS + 16 * N)
+        per_iter = 16 * N + (32 * N + s * NS) + 2 * s * NS + (s * NS + 8 * N) + 24 * N
+        setup = 24 * N + (8 * N + s * NS) + 2 * s * NS + (s * NS + 8 * N)
         return {"iter": per_iter * iters_total + 8 * N * (iters_total + solves) + setup * solves}
     return {
         "stencil": 16 * N * iters_total,
         "dstx_fwd": (32 * N + s * NS) * iters_total + (8 * N + s * NS) * solves,
         "dsty": 2 * (2 * s * NS) * applies if ny else 0,
         "time": 2 * s * NS * applies,
-        "dstx_inv": (s * NS + 16 * N) * applies,
+        "dstx_inv": (s * NS + 8 * N) * applies,
         "update": 24 * N * iters_total,
         "form": 8 * N * (iters_total + solves),
         "init": 24 * N * solves,

@@ -76,9 +76,8 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
  * wg[4] the fused x-y first and last passes, or 0 where the plan uses the separate
  * passes.  The fused passes serve square 2D grids whose whole level fits in LDS: one
  * workgroup per time level applies both spatial DSTs (Section 2.3's fast sine
- * transforms) there, so the y passes over memory disappear; their tile and wg[3]
- * follow fixed rules of the shape, since they carry the <q, P^{-1} q> sums
- * (ABAC_SLAB=0 in the environment keeps the separate passes).  wg[5] is 512 when
+ * transforms) there, so the y passes over memory disappear; their tile follows a fixed
+ * rule of the shape (ABAC_SLAB=0 in the environment keeps the separate passes).  wg[5] is 512 when
  * small 1D problems (nt * nx <= 4096) run each MINRES iteration as one launch, one
  * 512-thread workgroup per right-hand side doing every step in turn (launch latency,
  * not memory, bounds the separate kernels there; ABAC_SMALL=0 keeps them), else 0.  The other tiles are
@@ -88,15 +87,17 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
 abac_status abac_plan_tiles(abac_plan *plan, int *wg);
 
 /* Override the tiles the tuner chose for the plan's first x-DST pass (wg_x), y-DST pass
- * (wg_y, 2D only) and time pass (wg_t), in threads per workgroup; 0 keeps the current
- * choice.  These passes carry no reduction: every sequence of the fast transforms of
- * Section 2.3 is computed by the same arithmetic whatever the tile, so every legal tile
- * gives bitwise the same results, and this call lets a caller (a test) run each one.
+ * (wg_y, 2D only), time pass (wg_t) and last x-DST pass (wg_xi), in threads per
+ * workgroup; 0 keeps the current choice.  Every sequence of the fast transforms of
+ * Section 2.3 is computed by the same arithmetic whatever the tile, and the one
+ * reduction these passes carry in a MINRES solve (the time pass's partials of
+ * <q, P^{-1} q>) is summed in an order fixed by the sequence length, so every legal tile
+ * gives bitwise the same results; this call lets a caller (a test) run each one.
  * ABAC_EINVAL (nothing changed) if a tile is not legal for its kernel (it must be a
  * multiple of 64 and of the threads per sequence, and its LDS must fit the device), if
- * the plan uses the fused x-y passes and wg_x or wg_y is nonzero, for ABAC_PREC_NONE, or
- * while a solve is in progress.  Synchronises the plan stream. */
-abac_status abac_plan_set_tiles(abac_plan *plan, int wg_x, int wg_y, int wg_t);
+ * the plan uses the fused x-y passes and wg_x, wg_y or wg_xi is nonzero, for
+ * ABAC_PREC_NONE, or while a solve is in progress.  Synchronises the plan stream. */
+abac_status abac_plan_set_tiles(abac_plan *plan, int wg_x, int wg_y, int wg_t, int wg_xi);
 
 /* Release the plan (synchronises its stream; frees library-owned memory only). */
 abac_status abac_plan_destroy(abac_plan *plan);

@@ -108,7 +108,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abac_plan_set_coefficient.restype = I
     lib.abac_apply_Pinv_noalloc.argtypes = [I, I, I, D, D, I, I, VP, VP, VP]
     lib.abac_apply_Pinv_noalloc.restype = I
-    lib.abac_plan_set_tiles.argtypes = [P, I, I, I]
+    lib.abac_plan_set_tiles.argtypes = [P, I, I, I, I]
     lib.abac_plan_set_tiles.restype = I
     lib.abac_server_bytes_in_use.argtypes = [P]
     lib.abac_server_bytes_in_use.restype = SZ
@@ -317,11 +317,12 @@ class Plan:
         return {"dstx_fwd": wg[0], "dsty": wg[1], "time": wg[2], "dstx_inv": wg[3], "slab": wg[4],
                 "small": wg[5]}
 
-    def set_tiles(self, dstx_fwd: int = 0, dsty: int = 0, time: int = 0):
-        """Override the tuned tiles of the first x pass, the y pass and the time pass
-        (threads per workgroup; 0 keeps the current one).  Raises AbacError(EINVAL)
-        for a tile that is not legal for its kernel."""
-        _check(self._lib.abac_plan_set_tiles(self._h, int(dstx_fwd), int(dsty), int(time)), "abac_plan_set_tiles")
+    def set_tiles(self, dstx_fwd: int = 0, dsty: int = 0, time: int = 0, dstx_inv: int = 0):
+        """Override the tuned tiles of the first x pass, the y pass, the time pass and the
+        last x pass (threads per workgroup; 0 keeps the current one).  Raises
+        AbacError(EINVAL) for a tile that is not legal for its kernel."""
+        _check(self._lib.abac_plan_set_tiles(self._h, int(dstx_fwd), int(dsty), int(time), int(dstx_inv)),
+               "abac_plan_set_tiles")
 
     # -- kernel timing -----------------------------------------------------------
     def profile(self, on: bool = True):

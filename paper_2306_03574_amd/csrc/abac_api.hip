@@ -114,7 +114,7 @@ abac_status describe(int nx, int ny, int nt, double T, double alpha, int prec, i
   P.st_threads = std::min(kStencilThreads, (nx + 63) / 64 * 64);
   P.st_chunk = 32;
   while (P.st_chunk > 8 && stencil_blocks(P) < 512) P.st_chunk /= 2;
-  P.maxparts = std::max(stencil_blocks(P), std::max(update_blocks(P), (P.nt * P.ny1 + 1) / 2));
+  P.maxparts = std::max(std::max(stencil_blocks(P), update_blocks(P)), std::max((P.nt * P.ny1 + 1) / 2, P.ms / 2));
   P.maxparts = (P.maxparts + 63) & ~63;
   P.prec = prec;
   return ABAC_OK;
@@ -210,7 +210,8 @@ abac_status enqueue_pinv(abac_plan* p, const double* r, double* z, int minres_mo
   const int check = minres_mode != 0;
   const int fwd_mode = minres_mode == 2 ? FWD_LANCZOS : FWD_PLAIN;
   const double* in = minres_mode == 1 ? P.V[1] : r;
-  const int inv_mode = minres_mode == 0 ? INV_PLAIN : (minres_mode == 1 ? INV_GAMMA_INIT : INV_GAMMA_ITER);
+  // in MINRES mode the time pass forms <q, P^{-1} q> and the last pass writes z only
+  const int inv_mode = minres_mode == 0 ? INV_PLAIN : (minres_mode == 1 ? INV_Z_INIT : INV_Z_ITER);
   if (P.wg_s) {
     RUN(ABAC_K_DSTX_FWD, launch_dst2_fwd(P, p->prec, fwd_mode, check, in, p->stream));
     RUN(ABAC_K_TIME, launch_time(P, p->prec, check, p->stream));
@@ -388,9 +389,11 @@ abac_status autotune(DevPlan& P, int prec, hipStream_t s, int maxlds) {
     // a cached choice is used only if every tile is still legal for these kernels
     // (an entry written by another build of the library may not be)
     if (it != g_tune.end() && tile_fits(TK_XFWD, 2 * P.Mx, it->second[0], prec, maxlds) &&
-        it->second[1] == P.wg_xi && (!P.ny || tile_fits(TK_Y, 2 * P.My, it->second[2], prec, maxlds)) &&
+        tile_fits(TK_XINV, 2 * P.Mx, it->second[1], prec, maxlds) &&
+        (!P.ny || tile_fits(TK_Y, 2 * P.My, it->second[2], prec, maxlds)) &&
         tile_fits(TK_TIME, P.nt, it->second[3], prec, maxlds)) {
       P.wg_x = it->second[0];
+      P.wg_xi = it->second[1];
       P.wg_y = it->second[2];
       P.wg_t = it->second[3];
       return ABAC_OK;
@@ -428,9 +431,11 @@ abac_status autotune(DevPlan& P, int prec, hipStream_t s, int maxlds) {
     pick(TK_XFWD, 2 * P.Mx, &P.wg_x, [&] { return launch_dstx_fwd(P, prec, FWD_LANCZOS, 1, nullptr, s); });
     if (P.ny) pick(TK_Y, 2 * P.My, &P.wg_y, [&] { return launch_dsty(P, prec, 1, s); });
   }
+  // the time pass carries the <q, P^{-1} q> partials, summed in an order that does not
+  // depend on its tile, so it is timed like the others; so is the last pass, which in
+  // MINRES mode only writes z
   pick(TK_TIME, P.nt, &P.wg_t, [&] { return launch_time(P, prec, 1, s); });
-  // the last pass carries the <q, P^{-1} q> reduction: its tile stays at the fixed
-  // default so the summation order (and the iterates) never depend on timing noise
+  if (!P.wg_s) pick(TK_XINV, 2 * P.Mx, &P.wg_xi, [&] { return launch_dstx_inv(P, prec, INV_Z_ITER, nullptr, s); });
   HIP_TRY(hipMemsetAsync(P.st, 0, sizeof(MinresState) * P.B, s));
   HIP_TRY(hipStreamSynchronize(s));
   (void)hipGetLastError();
@@ -662,8 +667,8 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   P.wg_x = default_wg(TK_XFWD, 2 * P.Mx, prec, maxlds);
-  // the last pass carries a reduction, so its tile follows a fixed rule (not timing):
-  // the smallest legal tile, which keeps its LDS small and its occupancy high
+  // the last pass: the smallest legal tile until the tuner has timed the others (it
+  // keeps the LDS small and the occupancy high)
   P.wg_xi = 0;
   for (int wg : kTileCandidates)
     if (!P.wg_xi && tile_fits(TK_XINV, 2 * P.Mx, wg, prec, maxlds))
@@ -763,7 +768,9 @@ abac_status abac_plan_create(int nx, int ny, int nt, double T, double alpha, int
     if (own) (void)hipFree(ws);
     return hip_fail(e, "table upload");
   }
-  P.gamma_nparts = prec == ABAC_PREC_NONE ? update_blocks(P) : (P.wg_s ? P.nt : dstx_blocks(P, P.wg_xi));
+  // <q, P^{-1} q>: one partial per block of the identity kernel, or per mode pair of the
+  // time pass
+  P.gamma_nparts = prec == ABAC_PREC_NONE ? update_blocks(P) : P.ms / 2;
   if (prec != ABAC_PREC_NONE) {
     abac_status ts = autotune(P, prec, static_cast<hipStream_t>(stream), maxlds);
     if (ts != ABAC_OK) {
@@ -1131,7 +1138,7 @@ abac_status abac_profile_reset(abac_plan* p) {
   return ABAC_OK;
 }
 
-abac_status abac_plan_set_tiles(abac_plan* p, int wg_x, int wg_y, int wg_t) {
+abac_status abac_plan_set_tiles(abac_plan* p, int wg_x, int wg_y, int wg_t, int wg_xi) {
   g_last_error.clear();
   if (!p) return fail(ABAC_EINVAL, "plan is NULL");
   if (p->active) return fail(ABAC_EINVAL, "a solve is in progress on this plan");
@@ -1140,7 +1147,7 @@ abac_status abac_plan_set_tiles(abac_plan* p, int wg_x, int wg_y, int wg_t) {
   int dev = 0, maxlds = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  if ((wg_x || wg_y) && P.wg_s) return fail(ABAC_EINVAL, "the plan uses the fused x-y passes");
+  if ((wg_x || wg_y || wg_xi) && P.wg_s) return fail(ABAC_EINVAL, "the plan uses the fused x-y passes");
   if (wg_y && !P.ny) return fail(ABAC_EINVAL, "a 1D plan has no y pass");
   if (wg_x && !tile_fits(TK_XFWD, 2 * P.Mx, wg_x, p->prec, maxlds))
     return fail(ABAC_EINVAL, "x-DST tile " + std::to_string(wg_x) + " is not legal for this plan");
@@ -1148,7 +1155,10 @@ abac_status abac_plan_set_tiles(abac_plan* p, int wg_x, int wg_y, int wg_t) {
     return fail(ABAC_EINVAL, "y-DST tile " + std::to_string(wg_y) + " is not legal for this plan");
   if (wg_t && !tile_fits(TK_TIME, P.nt, wg_t, p->prec, maxlds))
     return fail(ABAC_EINVAL, "time tile " + std::to_string(wg_t) + " is not legal for this plan");
+  if (wg_xi && !tile_fits(TK_XINV, 2 * P.Mx, wg_xi, p->prec, maxlds))
+    return fail(ABAC_EINVAL, "last x-DST tile " + std::to_string(wg_xi) + " is not legal for this plan");
   HIP_TRY(hipStreamSynchronize(p->stream));
+  if (wg_xi) P.wg_xi = wg_xi;
   if (wg_x) P.wg_x = wg_x;
   if (wg_y) P.wg_y = wg_y;
   if (wg_t) P.wg_t = wg_t;

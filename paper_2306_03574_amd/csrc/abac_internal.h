@@ -191,7 +191,10 @@ enum StencilMode : int {
   STENCIL_PLAIN = 0, STENCIL_MINRES = 1, STENCIL_RESIDUAL = 2, STENCIL_REPORT = 3, STENCIL_T = 4, STENCIL_RESVEC = 5
 };
 enum FwdMode : int { FWD_PLAIN = 0, FWD_LANCZOS = 1 };
-enum InvMode : int { INV_PLAIN = 0, INV_GAMMA_INIT = 1, INV_GAMMA_ITER = 2 };
+// last pass: INV_PLAIN writes out; the MINRES set-up (INIT) and iteration (ITER) modes
+// write z_1 / z_{j+1} into its basis slot, with (GAMMA) or without (Z: the time pass
+// forms <q, P^{-1} q>) the partial sums of <q, p>
+enum InvMode : int { INV_PLAIN = 0, INV_GAMMA_INIT = 1, INV_GAMMA_ITER = 2, INV_Z_INIT = 3, INV_Z_ITER = 4 };
 enum FinKind : int {
   FIN_BNORM = 0, FIN_DELTA = 1, FIN_GAMMA_INIT = 2, FIN_GAMMA_ITER = 3, FIN_RES = 4, FIN_REPORT = 5,
   FIN_RNORM = 6,   // stopping test on the recurrence residual; decides forming u
@@ -243,7 +246,9 @@ hipError_t launch_fin(const DevPlan& P, int kind, double tol, int maxit, hipStre
 // check != 0: skip right-hand sides whose solve is not running
 hipError_t launch_dstx_fwd(const DevPlan& P, int prec, int mode, int check, const double* in, hipStream_t s);
 hipError_t launch_dsty(const DevPlan& P, int prec, int check, hipStream_t s);
-// inv1 = 1: the single time pass of C_alpha^{-1} (mu^{-1}, no time reversal)
+// inv1 = 1: the single time pass of C_alpha^{-1} (mu^{-1}, no time reversal); with check
+// (and inv1 = 0) the pass also writes the partials of <q, P^{-1} q> (PART_GAMMA, one
+// per mode pair)
 hipError_t launch_time(const DevPlan& P, int prec, int check, hipStream_t s, int inv1 = 0);
 hipError_t launch_dstx_inv(const DevPlan& P, int prec, int mode, double* out, hipStream_t s);
 // fused 2D first / last pass (square grids whose level fits in LDS; P.wg_s != 0)

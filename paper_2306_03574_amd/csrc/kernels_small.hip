@@ -108,8 +108,8 @@ __device__ __noinline__ void iter_small(const DevPlan& P, const double* __restri
     if (fin_begin(P, b, FIN_DELTA) && tid == 0) fin_scalar(P, b, FIN_DELTA, tot, 0.0, 0);
     __syncthreads();
   }
-  // Lanczos vector and z_{j+1} = P^{-1} q: x-DST (Lanczos fused), time pass, inverse
-  // x-DST with <q, p>, then gamma_{j+1} and the Givens step
+  // Lanczos vector and z_{j+1} = P^{-1} q: x-DST (Lanczos fused), time pass with the
+  // partials of <q, P^{-1} q>, inverse x-DST, then gamma_{j+1} and the Givens step
   if (st->state == ST_RUNNING) {
     constexpr int SX = seqs_of<T, L, WG>(), ST = seqs_of<T, NT, WG>();
     const int xtiles = (P.nt + 2 * SX - 1) / (2 * SX);
@@ -119,15 +119,14 @@ __device__ __noinline__ void iter_small(const DevPlan& P, const double* __restri
       __syncthreads();
     }
     for (int t = 0; t < ttiles; ++t) {
-      time_tile<T, NT, WG>(P, 0, b, t);
+      time_tile<T, NT, WG>(P, 0, b, t, 1);
       __syncthreads();
     }
-    double acc = 0.0;
+    const double tot = sum_parts(part_slot(P, PART_GAMMA, b), P.ms / 2);
     for (int t = 0; t < xtiles; ++t) {
-      acc += dstx_inv_tile<T, L, WG>(P, INV_GAMMA_ITER, nullptr, b, t, twx);
+      dstx_inv_tile<T, L, WG>(P, INV_Z_ITER, nullptr, b, t, twx);
       __syncthreads();
     }
-    const double tot = block_sum(acc);
     if (fin_begin(P, b, FIN_GAMMA_ITER) && tid == 0) fin_scalar(P, b, FIN_GAMMA_ITER, tot, 0.0, 0);
     __syncthreads();
   }
@@ -193,15 +192,14 @@ __device__ __noinline__ void setup_small(const DevPlan& P, const double* __restr
       __syncthreads();
     }
     for (int t = 0; t < ttiles; ++t) {
-      time_tile<T, NT, WG>(P, 0, b, t);
+      time_tile<T, NT, WG>(P, 0, b, t, 1);
       __syncthreads();
     }
-    double acc = 0.0;
+    tot = sum_parts(part_slot(P, PART_GAMMA, b), P.ms / 2);
     for (int t = 0; t < xtiles; ++t) {
-      acc += dstx_inv_tile<T, L, WG>(P, INV_GAMMA_INIT, nullptr, b, t, twx);
+      dstx_inv_tile<T, L, WG>(P, INV_Z_INIT, nullptr, b, t, twx);
       __syncthreads();
     }
-    tot = block_sum(acc);
   }
   if (fin_begin(P, b, FIN_GAMMA_INIT) && tid == 0) fin_scalar(P, b, FIN_GAMMA_INIT, tot, 0.0, 0);
 }

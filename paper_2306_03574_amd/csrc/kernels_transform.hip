@@ -47,8 +47,9 @@ __global__ void __launch_bounds__(WG)
 k_time(DevPlan P, int check, int inv1) {
   if (check && P.st[blockIdx.y].state != ST_RUNNING) return;
   // XCD-aware order: the blocks one XCD runs together read neighbouring column ranges of
-  // each time level, so partial cache lines are shared in its L2
-  time_tile<T, NT, WG>(P, inv1, blockIdx.y, xcd_remap(blockIdx.x, gridDim.x));
+  // each time level, so partial cache lines are shared in its L2.  In MINRES mode
+  // (check) the pass also forms the partials of <q, P^{-1} q>.
+  time_tile<T, NT, WG>(P, inv1, blockIdx.y, xcd_remap(blockIdx.x, gridDim.x), check && !inv1);
 }
 
 template <typename T, int L, int WG>
@@ -57,7 +58,7 @@ k_dstx_inv(DevPlan P, int mode, double* __restrict__ outp) {
   const int b = blockIdx.y;
   if (mode != INV_PLAIN && P.st[b].state != ST_RUNNING) return;
   const double acc = dstx_inv_tile<T, L, WG>(P, mode, outp, b, blockIdx.x, reinterpret_cast<const cplx<T>*>(P.twx));
-  if (mode == INV_PLAIN) return;
+  if (mode != INV_GAMMA_INIT && mode != INV_GAMMA_ITER) return;
   const double bs = block_sum(acc);
   if (threadIdx.x == 0) part_slot(P, PART_GAMMA, b)[blockIdx.x] = bs;
 }
@@ -225,13 +226,13 @@ k_dst2_inv(DevPlan P, int mode, double* __restrict__ outp) {
   const MinresState* st = P.st + b;
   if (mode != INV_PLAIN) {
     if (st->state != ST_RUNNING) return;
-    if (mode == INV_GAMMA_INIT) {
+    if (mode == INV_GAMMA_INIT || mode == INV_Z_INIT) {
       out = P.Z[zslot(1)] + off;
-      q = P.V[1] + off;
+      if (mode == INV_GAMMA_INIT) q = P.V[1] + off;
     } else {
       const int jj = st->iter + 1;
       out = P.Z[zslot(jj + 1)] + off;
-      q = P.V[(jj + 1) % 3] + off;
+      if (mode == INV_GAMMA_ITER) q = P.V[(jj + 1) % 3] + off;
     }
   }
   const int nx = M - 1, cnt = nx * M;
@@ -275,7 +276,7 @@ k_dst2_inv(DevPlan P, int mode, double* __restrict__ outp) {
       }
     }
   }
-  if (mode == INV_PLAIN) return;
+  if (mode != INV_GAMMA_INIT && mode != INV_GAMMA_ITER) return;
   const double bs = block_sum(acc);
   if (threadIdx.x == 0) part_slot(P, PART_GAMMA, b)[lvl] = bs;
 }

@@ -12,6 +12,14 @@ namespace {
 
 template <typename T, int L, int WG> constexpr int seqs_of() { return WG / fft_tps<T, L>(); }
 
+// LDS bytes of the time pass's partials of <q, P^{-1} q>: one per thread, then one per
+// group of G = min(8, TPS) threads of a sequence.
+template <typename T, int L, int WG>
+constexpr size_t time_red_bytes() {
+  constexpr int TPS = fft_tps<T, L>(), G = TPS >= 8 ? 8 : TPS;
+  return (size_t)(WG + WG / G) * sizeof(double);
+}
+
 // LDS bytes of one workgroup: the interleaved sequences; the inverse x pass reuses
 // the region for its FP64 output staging; the y pass (length <= 1024) also holds its
 // twiddle table, and the time pass its twiddles, spectral coefficients (A_k, B_k) and
@@ -26,7 +34,11 @@ constexpr size_t lds_of() {
   } else if constexpr (KIND == TK_Y) {
     return data + (size_t)L * c;
   } else if constexpr (KIND == TK_TIME) {
-    return data + (size_t)3 * L * c + (size_t)2 * L * sizeof(T);
+    // + the partials of <q, P^{-1} q> where they do not fit the (A_k, B_k) table, which
+    // they reuse once the weights are in registers
+    constexpr size_t tables = (size_t)3 * L * c + (size_t)2 * L * sizeof(T);
+    constexpr size_t red = time_red_bytes<T, L, WG>(), abk = (size_t)2 * L * c;
+    return data + tables + (red > abk ? red : 0);
   } else {
     return data;
   }
@@ -360,8 +372,17 @@ __device__ __forceinline__ void spectral_apply(cplx<T>* v, int j, cplx<T>* my, i
 // inv1 = 0: out = K Y K Y g with mu^{-1/2} (the ABAC P^{-1}); inv1 = 1: out = K g with
 // mu^{-1} and no time reversal (C_alpha^{-1} = S K S of eqs. (1.5)-(1.7)).
 // One block (S mode pairs, logical block index lbk) of right-hand side b.
+//
+// gamma != 0 (ABAC only): also the MINRES inner product <q, P^{-1} q>.  With
+// P^{-1} = C^{-1/2} (C^{-1/2})^T (eq. (1.9)) it equals ||(C^{-1/2})^T q||^2, and in the
+// sine basis (C^{-1/2})^T = Y K Y per mode, so <q, P^{-1} q> = ||K Y g||^2 summed over
+// the modes: the squared norm of the first factor's output, which this pass holds
+// anyway.  Each mode pair writes its sum to part_slot(PART_GAMMA)[pair]; the sum over a
+// pair runs in an order fixed by the sequence length (not by the tile), so the result
+// does not depend on the workgroup size.  Its LDS steps ride on the barriers the second
+// factor takes anyway.
 template <typename T, int NT, int WG>
-__device__ __forceinline__ void time_tile(const DevPlan& P, int inv1, int b, int lbk) {
+__device__ __forceinline__ void time_tile(const DevPlan& P, int inv1, int b, int lbk, int gamma = 0) {
   using C = cplx<T>;
   constexpr int R = FftShape<T, NT>::R, TPS = NT / R, S = seqs_of<T, NT, WG>();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -371,6 +392,14 @@ __device__ __forceinline__ void time_tile(const DevPlan& P, int inv1, int b, int
   T* sc = reinterpret_cast<T*>(abk + 2 * NT);
   T* sci = sc + NT;
   C* lds = reinterpret_cast<C*>(sci + NT);
+  // <q, P^{-1} q> partials: red[j S + s] per thread, red2[g S + s] per group of G threads;
+  // they take the (A_k, B_k) table's place (free once the weights are in registers, i.e.
+  // after the first FFT's first barrier) where it is large enough, else follow the
+  // sequences
+  constexpr int G = TPS >= 8 ? 8 : TPS;
+  constexpr bool red_in_abk = time_red_bytes<T, NT, WG>() <= (size_t)2 * NT * sizeof(C);
+  double* red = red_in_abk ? reinterpret_cast<double*>(abk) : reinterpret_cast<double*>(lds + S * NT);
+  double* red2 = red + WG;
   const int s = threadIdx.x % S, j = threadIdx.x / S;
   const int npairs = P.ms / 2;
   const int pair = lbk * S + s;
@@ -408,6 +437,17 @@ __device__ __forceinline__ void time_tile(const DevPlan& P, int inv1, int b, int
   spectral_apply<T, NT>(v, j, my, S, W);
   __syncthreads();
   fft_seq<T, NT, true>(v, j, my, S, tw);
+  double gsum = 0.0;   // with gamma: the pair's ||K Y g||^2, valid in thread j = 0
+  if (gamma) {
+    // this thread's part (K's output is a^{-t} v_t), published for the group sums below
+    double a = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const double sv = (double)sci[j + i * TPS];
+      a += sv * sv * ((double)v[i].x * v[i].x + (double)v[i].y * v[i].y);
+    }
+    red[j * S + s] = a;
+  }
   if (!inv1) {
     // D^{-1}, Y, D between the factors, y_t = a^{2t-nt+1} c_{nt-1-t}, without moving data:
     // with g_s = y_{nt-1-s} (an elementwise scaling of c), the DFT of y at frequency k is
@@ -420,19 +460,32 @@ __device__ __forceinline__ void time_tile(const DevPlan& P, int inv1, int b, int
       v[i] = cscale(v[i], sc[NT - 1 - t] * sci[t]);
     }
     __syncthreads();
+    if (gamma && j < TPS / G) {
+      // groups of G consecutive threads of a sequence (red is visible after the barrier
+      // above; red2 after the barriers inside the FFT below)
+      double a = 0.0;
+#pragma unroll
+      for (int q = 0; q < G; ++q) a += red[(j * G + q) * S + s];
+      red2[j * S + s] = a;
+    }
     fft_seq<T, NT, true>(v, j, my, S, tw);
     __syncthreads();
+    if (gamma && j == 0) {
+      for (int q = 0; q < TPS / G; ++q) gsum += red2[q * S + s];
+    }
     spectral_apply<T, NT>(v, j, my, S, W);
     __syncthreads();
     fft_seq<T, NT, true>(v, j, my, S, tw);
   }
-  if (!valid) return;
   const int shift = inv1 ? 0 : 1;
+  if (valid) {
 #pragma unroll
-  for (int i = 0; i < R; ++i) {
-    const int t = (j + i * TPS - shift) & (NT - 1);
-    g[(size_t)t * ld] = cscale(v[i], sci[t]);
+    for (int i = 0; i < R; ++i) {
+      const int t = (j + i * TPS - shift) & (NT - 1);
+      g[(size_t)t * ld] = cscale(v[i], sci[t]);
+    }
   }
+  if (gamma && j == 0 && valid) part_slot(P, PART_GAMMA, b)[pair] = gsum;
 }
 
 // ---------------------------------------------------------------------------
@@ -455,13 +508,13 @@ __device__ __forceinline__ double dstx_inv_tile(const DevPlan& P, int mode, doub
   const double* q = nullptr;
   const MinresState* st = P.st + b;
   if (mode != INV_PLAIN) {
-    if (mode == INV_GAMMA_INIT) {
+    if (mode == INV_GAMMA_INIT || mode == INV_Z_INIT) {
       out = P.Z[zslot(1)] + off;
-      q = P.V[1] + off;
+      if (mode == INV_GAMMA_INIT) q = P.V[1] + off;
     } else {
       const int jj = st->iter + 1;
       out = P.Z[zslot(jj + 1)] + off;
-      q = P.V[(jj + 1) % 3] + off;
+      if (mode == INV_GAMMA_ITER) q = P.V[(jj + 1) % 3] + off;
     }
   }
   const int nx = P.nx;

@@ -32,7 +32,7 @@ def test_byte_model_per_unit_figures():
     assert b["dstx_fwd"] == 6 * (32 * N + 8 * NS) + (8 * N + 8 * NS)
     assert b["dsty"] == 7 * 2 * 2 * 8 * NS
     assert b["time"] == 7 * 2 * 8 * NS
-    assert b["dstx_inv"] == 7 * (8 * NS + 16 * N)
+    assert b["dstx_inv"] == 7 * (8 * NS + 8 * N)
     assert b["update"] == 6 * 24 * N
     assert b["init"] == 24 * N
 

@@ -5,7 +5,7 @@ pass and the time pass and keeps the fastest, so the tile a benchmark run execut
 decided by timing.  Here each legal tile of each pass is forced (abac_plan_set_tiles)
 at every transform length the workloads use:
 
-* x-DST lengths 2(nx+1): 256 (the FP64 127^2 batch), 512 (255, 255^2), 1024 (511^2),
+* first and last x-DST lengths 2(nx+1): 256 (the FP64 127^2 batch), 512 (255, 255^2), 1024 (511^2),
   2048 (1D 1023), 8192 (1D 4095);
 * y-DST lengths 2(ny+1): 256, 512, 1024;
 * time lengths nt: 64, 128, 256, 512, 1024.
@@ -13,7 +13,8 @@ at every transform length the workloads use:
 For each tile: P_alpha^{-1} r against the FP64 oracle (FP64 transforms: 1e-10, the bar
 of the FP64 path; the D_alpha^{-1} scaling amplifies rounding by up to 1/alpha and at
 nt = 1024 the two FP64 routes differ by 4e-11; FP32 transforms: the FP32 bound), bitwise equality with the plan's tuned
-tile (the passes carry no reduction, so the arithmetic per sequence is the same), and
+tile (the arithmetic per sequence is the same, and the time pass sums its partials of
+<q, P^{-1} q> in an order fixed by the sequence length), and
 the Lanczos path of the first pass through a fixed number of MINRES iterations, whose
 iterate is bitwise equal to the tuned tile's and (FP64) within 1e-10 of the oracle's.
 The grids are small in the dimensions the pass does not transform.
@@ -55,7 +56,7 @@ def _rel(a, b):
 
 def _grid_for(kind, L):
     """A small grid whose pass `kind` has transform length L (separate x and y passes)."""
-    if kind == "dstx_fwd":
+    if kind in ("dstx_fwd", "dstx_inv"):
         nx = L // 2 - 1
         return (nx, 0, 8) if L > 1024 else (nx, 7, 8)
     if kind == "dsty":
@@ -63,8 +64,8 @@ def _grid_for(kind, L):
     return (15, 7, L)
 
 
-CASES = ([("dstx_fwd", L) for L in (256, 512, 1024, 2048, 8192)] + [("dsty", L) for L in (256, 512, 1024)] +
-         [("time", L) for L in (64, 128, 256, 512, 1024)])
+CASES = ([(k, L) for k in ("dstx_fwd", "dstx_inv") for L in (256, 512, 1024, 2048, 8192)] +
+         [("dsty", L) for L in (256, 512, 1024)] + [("time", L) for L in (64, 128, 256, 512, 1024)])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
