@@ -1,11 +1,14 @@
 """Summaries of rocprofv3 output for the committed profile records.
 
     python -m paper_2306_03574_amd.profiling trace <trace_dir> <out.md> --command "..."
+    python -m paper_2306_03574_amd.profiling sq <run_dir> [<run_dir> ...] --out <out.md> --kernels REGEX
+            --command "..." [--command ...] [--note "..."]
     python -m paper_2306_03574_amd.profiling pmc <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir>
             --copy-bytes B --workload NAME --prec fp64|fp32 --out-dir profiles --command "..." [--command ...]
 
 `trace` turns the kernel statistics of a `rocprofv3 --kernel-trace --stats` run into a
-short markdown table.  `pmc` turns two counter runs (`--pmc FETCH_SIZE`, then
+short markdown table.  `sq` turns one or more SQ counter runs (`--pmc SQ_...`) into per-wave instruction counts
+and VALU/LDS activity of selected kernels.  `pmc` turns two counter runs (`--pmc FETCH_SIZE`, then
 `--pmc WRITE_SIZE`) of the library and of a plain copy kernel of known size into HBM
 bytes per launch for each kernel of the library: the counters of the copy kernel give
 the factor that turns each counter into bytes (the copy reads and writes exactly
@@ -158,6 +161,75 @@ def summarize_pmc(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_byt
     return by_class
 
 
+def summarize_sq(run_dirs, out_md, kernel_regex, commands, note=""):
+    """Median per-dispatch SQ counters of the kernels matching `kernel_regex` over the
+    dispatches of one or more counter runs (each run may hold different counters), and
+    derived figures: instructions per wave, and the VALU busy fraction
+    SQ_ACTIVE_INST_VALU / SQ_BUSY_CU_CYCLES (one count per wave64 VALU instruction, i.e.
+    four cycles of its SIMD, against the cycles of the CU's four SIMDs).  Dispatches
+    that exit at once (speculative iterations: fewer than 1% of the kernel's largest
+    SQ_WAVE_CYCLES or SQ_BUSY_CU_CYCLES) are left out."""
+    import statistics
+    vals = OrderedDict()
+    meta = {}
+    for d in run_dirs:
+        path = _one(os.path.join(d, "**", "*counter_collection.csv"))
+        per_disp = OrderedDict()
+        for r in csv.DictReader(open(path)):
+            name = short_name(r["Kernel_Name"])
+            if not re.search(kernel_regex, name):
+                continue
+            key = (name, r["Dispatch_Id"])
+            per_disp.setdefault(key, {})[r["Counter_Name"]] = float(r["Counter_Value"])
+            meta[name] = dict(wg=int(r["Workgroup_Size"]), grid=int(r["Grid_Size"]), lds=int(r["LDS_Block_Size"]),
+                              vgpr=int(r["VGPR_Count"]), agpr=int(r["Accum_VGPR_Count"]),
+                              scratch=int(r["Scratch_Size"]))
+        sizes = {}
+        for (name, _), c in per_disp.items():
+            size = c.get("SQ_WAVE_CYCLES", c.get("SQ_BUSY_CU_CYCLES", 0.0))
+            sizes[name] = max(sizes.get(name, 0.0), size)
+        for (name, _), c in per_disp.items():
+            size = c.get("SQ_WAVE_CYCLES", c.get("SQ_BUSY_CU_CYCLES", 0.0))
+            if size < 0.01 * sizes[name]:
+                continue
+            for k, v in c.items():
+                vals.setdefault(name, OrderedDict()).setdefault(k, []).append(v)
+    lines = ["# SQ counters per dispatch (rocprofv3 --pmc)", "",
+             "Commands (from the repository root, on one MI355X), one counter set per run:", ""]
+    lines += [f"* `{c}`" for c in commands]
+    if note:
+        lines += ["", note]
+    lines += ["", "Median over the working dispatches of each kernel.  Per-wave figures divide by SQ_WAVES; "
+              "`VALU busy` is SQ_ACTIVE_INST_VALU / SQ_BUSY_CU_CYCLES (a wave64 VALU instruction keeps its "
+              "16-lane SIMD for 4 cycles; a CU has 4 SIMDs).", ""]
+    cols = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_LDS_BANK_CONFLICT",
+            "SQ_WAIT_INST_LDS", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_BUSY_CU_CYCLES", "SQ_WAVE_CYCLES",
+            "SQ_INSTS_VALU_TRANS_F32", "SQ_INSTS_VALU_TRANS_F64"]
+    lines += ["| kernel | wg | VGPR | scratch | dispatches | waves | VALU/wave | LDS/wave | VMEM rd/wave | "
+              "LDS bank conflicts | VALU busy |", "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    out = {}
+    for name, c in vals.items():
+        med = {k: statistics.median(v) for k, v in c.items()}
+        n = max(len(v) for v in c.values())
+        waves = med.get("SQ_WAVES")
+        def per_wave(k):
+            return f"{med[k] / waves:.0f}" if waves and k in med else "-"
+        busy = (f"{med['SQ_ACTIVE_INST_VALU'] / med['SQ_BUSY_CU_CYCLES']:.2f}"
+                if "SQ_ACTIVE_INST_VALU" in med and med.get("SQ_BUSY_CU_CYCLES") else "-")
+        m = meta[name]
+        lines.append(f"| `{name}` | {m['wg']} | {m['vgpr']} | {m['scratch']} | {n} | "
+                     f"{waves:.0f} | {per_wave('SQ_INSTS_VALU')} | {per_wave('SQ_INSTS_LDS')} | "
+                     f"{per_wave('SQ_INSTS_VMEM_RD')} | {med.get('SQ_LDS_BANK_CONFLICT', float('nan')):.3g} | {busy} |"
+                     if waves else f"| `{name}` | {m['wg']} | {m['vgpr']} | {m['scratch']} | {n} | - | - | - | - | - | {busy} |")
+        out[name] = {k: med[k] for k in cols if k in med}
+    lines += ["", "Raw medians:", ""]
+    for name, d in out.items():
+        lines.append(f"* `{name}`: " + ", ".join(f"{k} {v:.4g}" for k, v in d.items()))
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -166,6 +238,12 @@ def main():
     t.add_argument("out_md")
     t.add_argument("--command", required=True)
     t.add_argument("--note", default="")
+    q = sub.add_parser("sq")
+    q.add_argument("run_dirs", nargs="+")
+    q.add_argument("--out", required=True)
+    q.add_argument("--kernels", required=True)
+    q.add_argument("--command", action="append", required=True)
+    q.add_argument("--note", default="")
     p = sub.add_parser("pmc")
     for a in ("fetch_dir", "write_dir", "copy_fetch_dir", "copy_write_dir"):
         p.add_argument(a)
@@ -175,6 +253,10 @@ def main():
     p.add_argument("--out-dir", default=os.path.join(ROOT, "profiles"))
     p.add_argument("--command", action="append", required=True)
     a = ap.parse_args()
+    if a.cmd == "sq":
+        for name in summarize_sq(a.run_dirs, a.out, a.kernels, a.command, a.note):
+            print(name)
+        return
     if a.cmd == "trace":
         for r in summarize_trace(a.trace_dir, a.out_md, a.command, a.note):
             print(f"{r['kernel']:40s} {r['calls']:6d} {r['avg_us']:10.2f} us")
