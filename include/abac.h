@@ -195,6 +195,43 @@ abac_status abac_minres_advance(abac_plan *plan, int iterations);
 abac_status abac_minres_poll(abac_plan *plan, int *done);
 abac_status abac_minres_finish(abac_plan *plan, int *iters, double *relres, int *status);
 
+/* ---------------------------------------------------------------------------
+ * Groups: solves of different grids advanced together.  A group holds up to 64 plans
+ * (any mix of 1D and 2D grids, batches, alphas and final times; one transform
+ * precision), each with a solve begun by abac_minres_begin.  abac_group_advance runs
+ * one MINRES iteration (Section 3's solver) of every member with ONE launch per step
+ * of the iteration for all of them -- the matvec, the scalar steps, the three
+ * transform passes of Section 2.3 done twice, the residual recurrence and the
+ * stopping test -- instead of one launch per step per member, which is what bounds
+ * small grids.  Each member's results are bitwise those of its own solve
+ * (abac_minres_solve on the same plan): the same tiles compute the same values and
+ * every reduction is grouped as in the member's own kernels.
+ * ------------------------------------------------------------------------- */
+typedef struct abac_group abac_group;
+
+/* Create an empty group whose launches go to `stream` (a hipStream_t, NULL = the
+ * default stream).  Allocates a small device table (hipMalloc). */
+abac_status abac_group_create(void *stream, abac_group **out);
+
+/* Release the group (synchronises its stream); the member plans are not touched. */
+abac_status abac_group_destroy(abac_group *group);
+
+/* Set the members: n plans (0 <= n <= 64, no plan twice), each with a solve in progress
+ * (abac_minres_begin), the same transform precision (ABAC_PREC_FP64 or ABAC_PREC_FP32)
+ * and not on the one-launch small-problem path (abac_plan_tiles wg[5] = 0); a member's
+ * transform lengths must have 256-thread tiles (1D grids up to nx = 2047).  The
+ * group's stream waits for each member's stream (its set-up).  The plans' state is
+ * copied: a member must not be changed (abac_plan_set_coefficient, abac_plan_set_tiles)
+ * or advanced on its own while it is in the group.  ABAC_EINVAL otherwise.
+ * Synchronises the group's stream (the previous members' work). */
+abac_status abac_group_set(abac_group *group, abac_plan *const *plans, int n);
+
+/* Enqueue `iterations` MINRES iterations of every member (members that have stopped
+ * skip their work on the device), then make every member's stream wait for them.
+ * Afterwards abac_minres_poll and abac_minres_finish work on each member as after
+ * abac_minres_advance. */
+abac_status abac_group_advance(abac_group *group, int iterations);
+
 /* Restarted GMRES(restart) for the non-symmetric system T u = f with right
  * preconditioning by C_alpha (the block alpha-circulant preconditioner, which is not
  * symmetric and so needs a non-symmetric Krylov solver), x_0 = 0.  Stops at the first

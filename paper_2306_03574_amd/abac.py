@@ -27,7 +27,8 @@ EXPORTED = [
     "abac_status_string", "abac_last_error", "abac_fill_normal", "abac_server_create", "abac_server_destroy",
     "abac_server_submit", "abac_server_step", "abac_server_result", "abac_server_clock",
     "abac_server_bytes_in_use", "abac_plan_tiles", "abac_plan_set_coefficient", "abac_apply_T", "abac_apply_Cinv",
-    "abac_gmres_solve", "abac_plan_set_tiles", "abac_apply_Pinv_noalloc",
+    "abac_gmres_solve", "abac_plan_set_tiles", "abac_apply_Pinv_noalloc", "abac_group_create",
+    "abac_group_destroy", "abac_group_set", "abac_group_advance",
 ]
 
 _lib = None
@@ -108,6 +109,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abac_plan_set_coefficient.restype = I
     lib.abac_apply_Pinv_noalloc.argtypes = [I, I, I, D, D, I, I, VP, VP, VP]
     lib.abac_apply_Pinv_noalloc.restype = I
+    lib.abac_group_create.argtypes = [VP, ctypes.POINTER(P)]
+    lib.abac_group_create.restype = I
+    lib.abac_group_destroy.argtypes = [P]
+    lib.abac_group_destroy.restype = I
+    lib.abac_group_set.argtypes = [P, ctypes.POINTER(P), I]
+    lib.abac_group_set.restype = I
+    lib.abac_group_advance.argtypes = [P, I]
+    lib.abac_group_advance.restype = I
     lib.abac_plan_set_tiles.argtypes = [P, I, I, I, I]
     lib.abac_plan_set_tiles.restype = I
     lib.abac_server_bytes_in_use.argtypes = [P]
@@ -348,3 +357,39 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Group:
+    """Solves of different grids advanced together, one launch per MINRES step for all
+    members (abac_group_*).  Members are Plan objects with a solve begun (Plan.begin)."""
+
+    def __init__(self, device="cuda:0", stream: torch.cuda.Stream | None = None):
+        self._lib = load_library()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self._lib.abac_group_create(ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                   "abac_group_create")
+        self._h = h
+        self._members = []
+
+    def set(self, plans):
+        arr = (ctypes.c_void_p * max(len(plans), 1))(*[p._h.value for p in plans])
+        _check(self._lib.abac_group_set(self._h, arr, len(plans)), "abac_group_set")
+        self._members = list(plans)
+
+    def advance(self, iterations: int = 1):
+        _check(self._lib.abac_group_advance(self._h, int(iterations)), "abac_group_advance")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.abac_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

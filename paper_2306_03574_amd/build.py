@@ -13,12 +13,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libabac.so")
 SOURCES = ["abac_api.hip", "kernels_stencil.hip", "kernels_transform.hip", "kernels_small.hip", "kernels_gmres.hip",
-           "kernels_gen.hip", "server.hip"]
+           "kernels_gen.hip", "server.hip", "group.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # packed FP32 vector ops are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fuse within one source expression only (the language rule), never
+    # across statements: a device function then rounds the same way in every kernel it
+    # is inlined into, so solves advanced in a group match their solo runs bitwise
+    "-ffp-contract=on",
     "-Wno-unused-result",
 ]
 

@@ -463,6 +463,8 @@ abac_status plan_peek_snapshot(abac_plan* p, long long seq, int* ready, const Mi
 
 long long plan_snapshots_posted(const abac_plan* p) { return p->ring_posted; }
 
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
 }  // namespace abac
 
 namespace {

@@ -255,6 +255,8 @@ hipError_t launch_dstx_inv(const DevPlan& P, int prec, int mode, double* out, hi
 hipError_t launch_dst2_fwd(const DevPlan& P, int prec, int mode, int check, const double* in, hipStream_t s);
 hipError_t launch_dst2_inv(const DevPlan& P, int prec, int mode, double* out, hipStream_t s);
 int slab_wg(int nx, int ny, int prec, int maxlds, size_t margin);
+// dynamic LDS bytes of the fused 2D passes with workgroup wg (0 if not legal)
+size_t slab_lds_bytes(int L, int wg, int prec);
 // fused small-problem iteration (1D, nt * nx <= 4096; P.small != 0)
 hipError_t launch_iter_small(const DevPlan& P, int prec, const double* f, double* u, hipStream_t s);
 hipError_t launch_setup_small(const DevPlan& P, int prec, const double* f, double* u, double tol, int maxit,

@@ -140,11 +140,14 @@ ABAC_FFT_SHAPE(8192, 16, 2, 16)
 
 // The factorisation per precision.  FP64 values take twice the registers of FP32 ones,
 // so FP64 passes favour radix 8 (more threads per sequence, higher occupancy) and FP32
-// passes radix 16 (fewer exchanges through LDS): 512 = 16 x 2 x 16 in FP32 and
-// 1024 = 8 x 4 x 4 x 8 in FP64 differ from the shared table.
+// passes radix 16 (fewer exchanges through LDS): 512 = 16 x 2 x 16 in FP32, and
+// 256 = 8 x 4 x 8 and 1024 = 8 x 4 x 4 x 8 in FP64, differ from the shared table.
 template <typename T, int L> struct FftShape : FftShapeDefault<L> {};
 template <> struct FftShape<float, 512> {
   static constexpr int R = 16, m1 = 2, m2 = 0, passes = 3;
+};
+template <> struct FftShape<double, 256> {
+  static constexpr int R = 8, m1 = 4, m2 = 0, passes = 3;
 };
 template <> struct FftShape<double, 1024> {
   static constexpr int R = 8, m1 = 4, m2 = 4, passes = 4;

@@ -1,0 +1,439 @@
+// Solves of different grids advanced together: one launch per step of a MINRES
+// iteration (Section 3's solver: matvec, Lanczos step with the three transform steps of
+// Section 2.3 done twice, Givens QR, residual recurrence, stopping test) covers every
+// member of a group, whatever its grid, instead of one launch per step per solve.
+//
+// A launch's blocks are the concatenation of the members' blocks of that step: block w
+// finds its member r by a search over the step's prefix table, and runs the member's
+// tile (the same per-tile device code as the member's own kernels) for its grid.  All
+// list kernels use one workgroup size, kGroupWG threads (the scalar steps kFinThreads),
+// so the tile of a transform pass is the one of that size; those passes are computed by
+// the same arithmetic whatever the tile, the reductions are grouped as in the members'
+// own kernels (one partial per logical matvec or vector block, one per mode pair of
+// the time pass), and each member keeps its own state, partials and snapshots.  A
+// member's results are therefore bitwise those of its solo solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/abac.h"
+#include "abac_internal.h"
+#include "minres_device.h"
+#include "plan_internal.h"
+#include "stencil_device.h"
+#include "transform_device.h"
+
+namespace abac {
+namespace {
+
+constexpr int kGroupWG = 256;
+constexpr int kGroupFinThreads = 1024;   // as the members' scalar-step kernel
+constexpr int kGroupMax = 64;
+
+enum GroupStep : int { GS_STENCIL = 0, GS_XFWD, GS_Y, GS_TIME, GS_XINV, GS_VEC, GS_FIN, GS_COUNT };
+
+struct GroupMember {
+  DevPlan P;
+  const double* f;
+  double* u;
+};
+
+// Device table of a group: the members and, per step, the first block of each member
+// (off[step][n] = the launch's block count).
+struct GroupTable {
+  GroupMember m[kGroupMax];
+  int off[GS_COUNT][kGroupMax + 1];
+  int n;
+};
+
+// Member and block of block w of a step: r with off[r] <= w < off[r+1], then right-hand
+// side b and the block lbk within it (per = blocks per right-hand side).
+struct Where {
+  int r, b, lbk, per;
+};
+
+__device__ __forceinline__ Where locate(const GroupTable* __restrict__ G, int step, int w) {
+  const int* off = G->off[step];
+  int lo = 0, hi = G->n;   // off[lo] <= w < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= w) lo = mid;
+    else hi = mid;
+  }
+  Where at;
+  at.r = lo;
+  const int nb = G->m[lo].P.B;
+  at.per = (off[lo + 1] - off[lo]) / nb;
+  const int lw = w - off[lo];
+  at.b = lw / at.per;
+  at.lbk = lw - at.b * at.per;
+  return at;
+}
+
+// ---- matvec: one logical block per workgroup, lanes beyond the member's column tile
+// idle (they add 0 to the block's sum, so the partial is the member kernel's) ---------
+template <int MODE>
+__global__ void __launch_bounds__(kGroupWG) k_group_stencil(const GroupTable* __restrict__ G) {
+  const Where at = locate(G, GS_STENCIL, blockIdx.x);
+  const GroupMember& M = G->m[at.r];
+  const DevPlan& P = M.P;
+  const MinresState* st = P.st + at.b;
+  if (st->state != ST_RUNNING) return;
+  if (MODE == STENCIL_RESIDUAL && !st->need_check) return;
+  const size_t off = (size_t)at.b * P.N;
+  double acc = 0.0;
+  const bool lane = (int)threadIdx.x < P.st_threads;
+  if (MODE == STENCIL_MINRES) {
+    const int j = st->iter + 1;
+    const double* x = P.Z[zslot(j)] + off;
+    double* y = P.V[(j + 1) % 3] + off;
+    if (lane)
+      acc = P.coef_x ? stencil_run<true, OUT_REV, true>(P, x, y, nullptr, at.lbk, at.per, threadIdx.x, true)
+                     : stencil_run<false, OUT_REV, true>(P, x, y, nullptr, at.lbk, at.per, threadIdx.x, true);
+  } else {
+    const double* x = M.u + off;
+    const double* f = M.f + off;
+    if (lane)
+      acc = P.coef_x ? stencil_run<true, OUT_RESNORM, false>(P, x, nullptr, f, at.lbk, at.per, threadIdx.x, true)
+                     : stencil_run<false, OUT_RESNORM, false>(P, x, nullptr, f, at.lbk, at.per, threadIdx.x, true);
+  }
+  const double bs = block_sum(acc);
+  if (threadIdx.x == 0) part_slot(P, MODE == STENCIL_MINRES ? PART_DELTA : PART_RES, at.b)[at.lbk] = bs;
+}
+
+// ---- scalar steps: one workgroup per right-hand side --------------------------------
+__global__ void __launch_bounds__(kGroupFinThreads) k_group_fin(const GroupTable* __restrict__ G, int kind) {
+  const Where at = locate(G, GS_FIN, blockIdx.x);
+  const DevPlan& P = G->m[at.r].P;
+  if (!fin_begin(P, at.b, kind)) return;
+  int nparts;
+  switch (kind) {
+    case FIN_BNORM:
+    case FIN_RNORM: nparts = G->off[GS_VEC][at.r + 1] - G->off[GS_VEC][at.r]; nparts /= P.B; break;
+    case FIN_DELTA: nparts = stencil_blocks(P); break;
+    case FIN_GAMMA_INIT:
+    case FIN_GAMMA_ITER: nparts = P.gamma_nparts; break;
+    default: nparts = stencil_blocks(P); break;
+  }
+  const double tot = sum_parts(part_slot(P, fin_part_kind(kind), at.b), nparts);
+  if (threadIdx.x == 0) fin_scalar(P, at.b, kind, tot, 0.0, 0);
+}
+
+// ---- vector steps: residual recurrence, iterate from the basis ----------------------
+__global__ void __launch_bounds__(kGroupWG) k_group_update(const GroupTable* __restrict__ G) {
+  const Where at = locate(G, GS_VEC, blockIdx.x);
+  const GroupMember& M = G->m[at.r];
+  const DevPlan& P = M.P;
+  if (P.st[at.b].state != ST_RUNNING) return;
+  const double acc = update_part(P, at.b, M.u, at.lbk, at.per);
+  const double bs = block_sum(acc);
+  if (threadIdx.x == 0) part_slot(P, PART_RNORM, at.b)[at.lbk] = bs;
+}
+
+__global__ void __launch_bounds__(kGroupWG) k_group_form(const GroupTable* __restrict__ G) {
+  const Where at = locate(G, GS_VEC, blockIdx.x);
+  const GroupMember& M = G->m[at.r];
+  const DevPlan& P = M.P;
+  const MinresState* st = P.st + at.b;
+  if (!st->form_now) return;
+  const int nb = st->nbasis;
+  if (st->flush_now) form_dispatch<true>(P, at.b, nb, M.u, at.lbk, at.per);
+  else form_dispatch<false>(P, at.b, nb, M.u, at.lbk, at.per);
+}
+
+// ---- transform passes: the member's tile of its own length, selected at run time ----
+#define ABAC_GROUP_X_LENGTHS(CASE) CASE(16) CASE(32) CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096)
+#define ABAC_GROUP_SLAB_LENGTHS(CASE) CASE(16) CASE(32) CASE(64) CASE(128) CASE(256)
+#define ABAC_GROUP_T_LENGTHS(CASE) CASE(8) CASE(16) CASE(32) CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024)
+
+// first pass: the Lanczos step and the x-DST, or the fused x-y pass
+template <typename T>
+__global__ void __launch_bounds__(kGroupWG) k_group_xfwd(const GroupTable* __restrict__ G) {
+  const Where at = locate(G, GS_XFWD, blockIdx.x);
+  const DevPlan& P = G->m[at.r].P;
+  if (P.st[at.b].state != ST_RUNNING) return;
+  constexpr int mode = FWD_LANCZOS;
+  const double* in = nullptr;
+  const int L = 2 * P.Mx;
+  if (P.wg_s) {
+#define CASE(LL) \
+    case LL: if constexpr (slab_ok<T, LL, kGroupWG>()) dst2_fwd_tile<T, LL, kGroupWG>(P, mode, in, at.b, at.lbk); break;
+    switch (L) { ABAC_GROUP_SLAB_LENGTHS(CASE) default: break; }
+#undef CASE
+  } else {
+#define CASE(LL)                                                                                            \
+    case LL:                                                                                                \
+      if constexpr (tile_ok<T, LL, kGroupWG, TK_XFWD>())                                                    \
+        dstx_fwd_tile<T, LL, kGroupWG>(P, mode, in, at.b, at.lbk, reinterpret_cast<const cplx<T>*>(P.twx)); \
+      break;
+    switch (L) { ABAC_GROUP_X_LENGTHS(CASE) default: break; }
+#undef CASE
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kGroupWG) k_group_y(const GroupTable* __restrict__ G) {
+  const Where at = locate(G, GS_Y, blockIdx.x);
+  const DevPlan& P = G->m[at.r].P;
+  if (P.st[at.b].state != ST_RUNNING) return;
+  const int lbk = xcd_remap(at.lbk, at.per);
+#define CASE(LL) \
+  case LL: if constexpr (tile_ok<T, LL, kGroupWG, TK_Y>()) dsty_tile<T, LL, kGroupWG>(P, at.b, lbk); break;
+  switch (2 * P.My) { ABAC_GROUP_X_LENGTHS(CASE) default: break; }
+#undef CASE
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kGroupWG) k_group_time(const GroupTable* __restrict__ G) {
+  const Where at = locate(G, GS_TIME, blockIdx.x);
+  const DevPlan& P = G->m[at.r].P;
+  if (P.st[at.b].state != ST_RUNNING) return;
+  const int lbk = xcd_remap(at.lbk, at.per);
+#define CASE(LL) \
+  case LL: if constexpr (tile_ok<T, LL, kGroupWG, TK_TIME>()) time_tile<T, LL, kGroupWG>(P, 0, at.b, lbk, 1); break;
+  switch (P.nt) { ABAC_GROUP_T_LENGTHS(CASE) default: break; }
+#undef CASE
+}
+
+// last pass: writes z_{j+1}; <q, P^{-1} q> came from the time pass
+template <typename T>
+__global__ void __launch_bounds__(kGroupWG) k_group_xinv(const GroupTable* __restrict__ G) {
+  constexpr int mode = INV_Z_ITER;
+  const Where at = locate(G, GS_XINV, blockIdx.x);
+  const DevPlan& P = G->m[at.r].P;
+  if (P.st[at.b].state != ST_RUNNING) return;
+  const int L = 2 * P.Mx;
+  if (P.wg_s) {
+#define CASE(LL) \
+    case LL: if constexpr (slab_ok<T, LL, kGroupWG>()) (void)dst2_inv_tile<T, LL, kGroupWG>(P, mode, nullptr, at.b, at.lbk); break;
+    switch (L) { ABAC_GROUP_SLAB_LENGTHS(CASE) default: break; }
+#undef CASE
+  } else {
+#define CASE(LL)                                                                                                     \
+    case LL:                                                                                                         \
+      if constexpr (tile_ok<T, LL, kGroupWG, TK_XINV>())                                                             \
+        (void)dstx_inv_tile<T, LL, kGroupWG>(P, mode, nullptr, at.b, at.lbk, reinterpret_cast<const cplx<T>*>(P.twx)); \
+      break;
+    switch (L) { ABAC_GROUP_X_LENGTHS(CASE) default: break; }
+#undef CASE
+  }
+}
+
+#undef ABAC_GROUP_X_LENGTHS
+#undef ABAC_GROUP_SLAB_LENGTHS
+#undef ABAC_GROUP_T_LENGTHS
+
+}  // namespace
+}  // namespace abac
+
+using namespace abac;
+
+struct abac_group {
+  hipStream_t stream;
+  int prec;
+  GroupTable* d_table;           // device copy
+  std::vector<GroupTable> h;     // host copy (one element)
+  std::vector<abac_plan*> members;
+  int blocks[GS_COUNT];
+  size_t lds[GS_COUNT];
+  hipEvent_t joined;             // members' set-up done (recorded on each member stream in turn)
+  hipEvent_t done;               // the group's last enqueued work
+};
+
+namespace {
+
+abac_status gfail(abac_status s, const std::string& msg) {
+  set_last_error(msg);
+  return s;
+}
+
+#define GHIP(expr)                                                                          \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return gfail(ABAC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Blocks per right-hand side of each step for a member's plan, and the dynamic LDS its
+// tiles need at kGroupWG threads; false if a tile of that size is not legal for it.
+bool member_shape(const DevPlan& P, int prec, int blocks[GS_COUNT], size_t lds[GS_COUNT]) {
+  for (int k = 0; k < GS_COUNT; ++k) {
+    blocks[k] = 0;
+    lds[k] = 0;
+  }
+  const int Lx = 2 * P.Mx, Ly = 2 * P.My;
+  blocks[GS_STENCIL] = stencil_blocks(P);
+  blocks[GS_VEC] = update_blocks(P);
+  blocks[GS_FIN] = 1;
+  if (P.wg_s) {
+    const size_t l = slab_lds_bytes(Lx, kGroupWG, prec);
+    if (!l) return false;
+    blocks[GS_XFWD] = blocks[GS_XINV] = P.nt;
+    lds[GS_XFWD] = lds[GS_XINV] = l;
+  } else {
+    if (!transform_tile_valid(TK_XFWD, Lx, kGroupWG, prec) || !transform_tile_valid(TK_XINV, Lx, kGroupWG, prec))
+      return false;
+    const int S = kGroupWG / transform_tps(Lx, prec);
+    blocks[GS_XFWD] = blocks[GS_XINV] = (P.nt * P.ny1 + 2 * S - 1) / (2 * S);
+    lds[GS_XFWD] = transform_lds_bytes(TK_XFWD, Lx, kGroupWG, prec);
+    lds[GS_XINV] = transform_lds_bytes(TK_XINV, Lx, kGroupWG, prec);
+    if (P.ny) {
+      if (!transform_tile_valid(TK_Y, Ly, kGroupWG, prec)) return false;
+      const int Sy = kGroupWG / transform_tps(Ly, prec);
+      blocks[GS_Y] = ((P.Mx / 2 + Sy - 1) / Sy) * P.nt;
+      lds[GS_Y] = transform_lds_bytes(TK_Y, Ly, kGroupWG, prec);
+    }
+  }
+  if (!transform_tile_valid(TK_TIME, P.nt, kGroupWG, prec)) return false;
+  const int St = kGroupWG / transform_tps(P.nt, prec);
+  blocks[GS_TIME] = (P.ms / 2 + St - 1) / St;
+  lds[GS_TIME] = transform_lds_bytes(TK_TIME, P.nt, kGroupWG, prec);
+  return true;
+}
+
+template <typename K, typename... A>
+abac_status group_launch(abac_group* g, int step, int threads, K kernel, A... args) {
+  if (!g->blocks[step]) return ABAC_OK;
+  hipLaunchKernelGGL(kernel, dim3(g->blocks[step]), dim3(threads), g->lds[step], g->stream, g->d_table, args...);
+  GHIP(hipGetLastError());
+  return ABAC_OK;
+}
+
+#define GRUN(expr)                   \
+  do {                               \
+    abac_status s_ = (expr);         \
+    if (s_ != ABAC_OK) return s_;    \
+  } while (0)
+
+template <typename T>
+abac_status group_iteration(abac_group* g) {
+  GRUN(group_launch(g, GS_STENCIL, kGroupWG, k_group_stencil<STENCIL_MINRES>));
+  GRUN(group_launch(g, GS_FIN, kGroupFinThreads, k_group_fin, (int)FIN_DELTA));
+  GRUN(group_launch(g, GS_XFWD, kGroupWG, k_group_xfwd<T>));
+  GRUN(group_launch(g, GS_Y, kGroupWG, k_group_y<T>));
+  GRUN(group_launch(g, GS_TIME, kGroupWG, k_group_time<T>));
+  GRUN(group_launch(g, GS_Y, kGroupWG, k_group_y<T>));
+  GRUN(group_launch(g, GS_XINV, kGroupWG, k_group_xinv<T>));
+  GRUN(group_launch(g, GS_FIN, kGroupFinThreads, k_group_fin, (int)FIN_GAMMA_ITER));
+  GRUN(group_launch(g, GS_VEC, kGroupWG, k_group_update));
+  GRUN(group_launch(g, GS_FIN, kGroupFinThreads, k_group_fin, (int)FIN_RNORM));
+  GRUN(group_launch(g, GS_VEC, kGroupWG, k_group_form));
+  GRUN(group_launch(g, GS_STENCIL, kGroupWG, k_group_stencil<STENCIL_RESIDUAL>));
+  GRUN(group_launch(g, GS_FIN, kGroupFinThreads, k_group_fin, (int)FIN_RES));
+  return ABAC_OK;
+}
+
+// every member's stream waits for the group's work so far (later calls on a member,
+// such as abac_minres_finish, are ordered after it)
+abac_status group_release(abac_group* g) {
+  GHIP(hipEventRecord(g->done, g->stream));
+  for (abac_plan* p : g->members) GHIP(hipStreamWaitEvent(p->stream, g->done, 0));
+  return ABAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+abac_status abac_group_create(void* stream, abac_group** out) {
+  if (!out) return gfail(ABAC_EINVAL, "out is NULL");
+  *out = nullptr;
+  abac_group* g = new abac_group();
+  g->stream = static_cast<hipStream_t>(stream);
+  g->prec = -1;
+  g->h.resize(1);
+  std::memset(g->h.data(), 0, sizeof(GroupTable));
+  std::memset(g->blocks, 0, sizeof(g->blocks));
+  std::memset(g->lds, 0, sizeof(g->lds));
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&g->d_table), sizeof(GroupTable));
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&g->joined, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&g->done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (g->d_table) (void)hipFree(g->d_table);
+    delete g;
+    return gfail(ABAC_ENOMEM, std::string("group set-up: ") + hipGetErrorString(e));
+  }
+  *out = g;
+  return ABAC_OK;
+}
+
+abac_status abac_group_destroy(abac_group* g) {
+  if (!g) return ABAC_OK;
+  (void)hipStreamSynchronize(g->stream);
+  (void)hipEventDestroy(g->joined);
+  (void)hipEventDestroy(g->done);
+  (void)hipFree(g->d_table);
+  delete g;
+  return ABAC_OK;
+}
+
+abac_status abac_group_set(abac_group* g, abac_plan* const* plans, int n) {
+  set_last_error("");
+  if (!g || (n && !plans)) return gfail(ABAC_EINVAL, "NULL argument");
+  if (n < 0 || n > kGroupMax) return gfail(ABAC_EINVAL, "a group holds 0.." + std::to_string(kGroupMax) + " plans");
+  GroupTable& H = g->h[0];
+  std::memset(&H, 0, sizeof(GroupTable));
+  int prec = -1;
+  int blocks[GS_COUNT], total[GS_COUNT] = {0};
+  size_t lds[GS_COUNT], lmax[GS_COUNT] = {0};
+  for (int r = 0; r < n; ++r) {
+    abac_plan* p = plans[r];
+    if (!p) return gfail(ABAC_EINVAL, "NULL plan in the group");
+    for (int q = 0; q < r; ++q)
+      if (plans[q] == p) return gfail(ABAC_EINVAL, "a plan appears twice in the group");
+    if (!p->active) return gfail(ABAC_EINVAL, "every member needs a solve begun with abac_minres_begin");
+    if (p->prec == ABAC_PREC_NONE) return gfail(ABAC_EINVAL, "members need a preconditioner (FP64 or FP32 transforms)");
+    if (p->P.small) return gfail(ABAC_EINVAL, "small 1D plans already run an iteration in one launch");
+    if (prec >= 0 && p->prec != prec) return gfail(ABAC_EINVAL, "members must share the transform precision");
+    prec = p->prec;
+    if (!member_shape(p->P, p->prec, blocks, lds))
+      return gfail(ABAC_EINVAL, "a member's transform lengths have no " + std::to_string(kGroupWG) + "-thread tile");
+    H.m[r].P = p->P;
+    H.m[r].f = p->f;
+    H.m[r].u = p->u;
+    for (int k = 0; k < GS_COUNT; ++k) {
+      H.off[k][r] = total[k];
+      total[k] += blocks[k] * p->P.B;
+      lmax[k] = std::max(lmax[k], lds[k]);
+    }
+  }
+  for (int k = 0; k < GS_COUNT; ++k) {
+    H.off[k][n] = total[k];
+    g->blocks[k] = n ? total[k] : 0;
+    g->lds[k] = lmax[k];
+  }
+  H.n = n;
+  // the previous table may still be read by enqueued work
+  GHIP(hipStreamSynchronize(g->stream));
+  GHIP(hipMemcpy(g->d_table, &H, sizeof(GroupTable), hipMemcpyHostToDevice));
+  g->members.assign(plans, plans + n);
+  g->prec = prec;
+  // the group's launches follow each member's set-up on its own stream
+  for (abac_plan* p : g->members) {
+    GHIP(hipEventRecord(g->joined, p->stream));
+    GHIP(hipStreamWaitEvent(g->stream, g->joined, 0));
+  }
+  return ABAC_OK;
+}
+
+abac_status abac_group_advance(abac_group* g, int iterations) {
+  set_last_error("");
+  if (!g) return gfail(ABAC_EINVAL, "NULL group");
+  if (iterations < 0) return gfail(ABAC_EINVAL, "iterations must be >= 0");
+  for (abac_plan* p : g->members)
+    if (!p->active) return gfail(ABAC_EINVAL, "a member's solve was finished; set the group again");
+  for (int it = 0; it < iterations && !g->members.empty(); ++it) {
+    GRUN(g->prec == ABAC_PREC_FP32 ? group_iteration<float>(g) : group_iteration<double>(g));
+    // each member's snapshot of this iteration is complete behind this point
+    for (abac_plan* p : g->members) {
+      const int slot = (int)(p->ring_posted % kSnapRing);
+      GHIP(hipEventRecord(p->ring_ev[slot], g->stream));
+      p->ring_posted++;
+    }
+  }
+  return group_release(g);
+}
+
+}  // extern "C"

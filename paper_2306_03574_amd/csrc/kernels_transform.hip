@@ -63,222 +63,29 @@ k_dstx_inv(DevPlan P, int mode, double* __restrict__ outp) {
   if (threadIdx.x == 0) part_slot(P, PART_GAMMA, b)[blockIdx.x] = bs;
 }
 
-// ---------------------------------------------------------------------------
-// fused 2D passes, for square grids whose whole (y, x) level fits in LDS: one block
-// per time level applies the DST-I along x and along y in LDS, so the y passes over
-// HBM disappear (three transform passes per apply instead of five).  The level stays
-// in LDS as [ny][Mx] in the transform precision (column Mx-1 the zero pad, as in the
-// scratch layout, rows padded to Mx+1 entries so that the rows and the columns of
-// neighbouring sequences fall in different LDS banks); its lines go through a separate
-// exchange area, S sequences at a time.
-// ---------------------------------------------------------------------------
-template <typename T, int L>
-constexpr size_t slab_bytes() {
-  return ((size_t)(L / 2 - 1) * (L / 2 + 1) * sizeof(T) + 15) / 16 * 16;
-}
-
-template <typename T, int L, int WG>
-constexpr size_t slab_lds_of() {
-  return slab_bytes<T, L>() + (size_t)seqs_of<T, L, WG>() * L * sizeof(cplx<T>);
-}
-
-template <typename T, int L, int WG>
-constexpr bool slab_ok() {
-  return L >= 16 && L <= 256 && WG >= fft_tps<T, L>() && WG % fft_tps<T, L>() == 0 && WG % 64 == 0 &&
-         slab_lds_of<T, L, WG>() <= kMaxTransformLds;
-}
-
-// Orthonormal DST-I, in place, of `nlines` lines of the level held in LDS (ROWS: the
-// rows, element e of row l at slab[l (Mx+1) + e]; otherwise the columns, element e of
-// column l at slab[e (Mx+1) + l]).  Lines of length M-1 = L/2-1 go two to a complex
-// sequence of length L (odd extension); the transform of the first is minus the
-// imaginary part, of the second the real part.  Rows write 0 to the pad column.
-// All threads call it together; it ends with a barrier.
-template <typename T, int L, int WG, bool ROWS>
-__device__ __forceinline__ void slab_dst(T* slab, int nlines, cplx<T>* exch, const cplx<T>* __restrict__ tw) {
-  using C = cplx<T>;
-  constexpr int R = FftShape<T, L>::R, TPS = L / R, S = seqs_of<T, L, WG>(), M = L / 2, LD = M + 1;
-  const int s = threadIdx.x % S, j = threadIdx.x / S;
-  const int npairs = (nlines + 1) / 2;
-  const T scl = (T)(1.0 / sqrt((double)L));
-  for (int p0 = 0; p0 < npairs; p0 += S) {
-    const int p = p0 + s;
-    const bool va = 2 * p < nlines, vb = 2 * p + 1 < nlines;
-    const int la = min(2 * p, nlines - 1), lb = min(2 * p + 1, nlines - 1);
-    C v[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int t = j + i * TPS;
-      const int e = t < M ? max(t - 1, 0) : min(2 * M - t - 1, M - 2);
-      const T a = slab[ROWS ? la * LD + e : e * LD + la];
-      const T c = slab[ROWS ? lb * LD + e : e * LD + lb];
-      const bool zero = t == 0 || t == M;
-      const T sg = t < M ? (T)1 : (T)-1;
-      v[i] = C{zero || !va ? (T)0 : sg * a, zero || !vb ? (T)0 : sg * c};
-    }
-    __syncthreads();   // the previous round's last reads of the exchange area are done
-    fft_seq<T, L, false>(v, j, exch + s, S, tw);
-#pragma unroll
-    for (int i = 0; i <= R / 2; ++i) {
-      const int k = j + i * TPS;
-      if (k == 0 || k > M) continue;
-      if (k == M) {
-        if (ROWS) {
-          if (va) slab[la * LD + M - 1] = 0;
-          if (vb) slab[lb * LD + M - 1] = 0;
-        }
-        continue;
-      }
-      const int e = k - 1;
-      if (va) slab[ROWS ? la * LD + e : e * LD + la] = -v[i].y * scl;
-      if (vb) slab[ROWS ? lb * LD + e : e * LD + lb] = v[i].x * scl;
-    }
-  }
-  __syncthreads();
-}
-
+// fused 2D passes (square grids whose level fits in LDS; tile bodies in
+// transform_device.h): one block per time level
 // first pass, fused: (Lanczos step,) DST-I along x and y of one level, level written
 // to the scratch.  Modes and checks as in k_dstx_fwd.
 template <typename T, int L, int WG>
 __global__ void __launch_bounds__(WG)
 k_dst2_fwd(DevPlan P, int mode, int check, const double* __restrict__ in) {
-  using C = cplx<T>;
-  constexpr int M = L / 2;
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* slab = reinterpret_cast<T*>(smem);
-  C* exch = reinterpret_cast<C*>(smem + slab_bytes<T, L>());
-  const int b = blockIdx.y, lvl = blockIdx.x;
-  const size_t off = (size_t)b * P.N;
-  const double* src = in ? in + off : nullptr;
-  double* qout = nullptr;
-  const double* vj = nullptr;
-  const double* vjm1 = nullptr;
-  double cA = 1.0, cB = 0.0, cC = 0.0;
-  if (check || mode == FWD_LANCZOS) {
-    const MinresState* st = P.st + b;
-    if (st->state != ST_RUNNING) return;
-    if (mode == FWD_LANCZOS) {
-      const int j = st->iter + 1;
-      qout = P.V[(j + 1) % 3] + off;
-      src = qout;
-      vj = P.V[j % 3] + off;
-      vjm1 = P.V[j == 1 ? j % 3 : (j + 2) % 3] + off;   // v_0 has weight 0 at j = 1
-      cA = st->sig;
-      cB = st->delta * st->sig;
-      cC = st->gamma * st->sig_prev;
-    }
-  }
-  const int nx = M - 1, cnt = nx * nx;
-  const size_t base = (size_t)lvl * P.m;
-  // stage the level; a thread's BATCH loads (clamped, so unconditional) are issued
-  // before any is used
-  constexpr int BATCH = 8;
-  for (int e0 = 0; e0 < cnt; e0 += BATCH * WG) {
-    double a[BATCH], bv[BATCH], cv[BATCH];
-#pragma unroll
-    for (int u = 0; u < BATCH; ++u) {
-      const size_t e = base + min(e0 + (int)threadIdx.x + u * WG, cnt - 1);
-      a[u] = src[e];
-      if (mode == FWD_LANCZOS) {
-        bv[u] = vj[e];
-        cv[u] = vjm1[e];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < BATCH; ++u) {
-      const int e = e0 + (int)threadIdx.x + u * WG;
-      if (e < cnt) {
-        double q = a[u];
-        if (mode == FWD_LANCZOS) {
-          q = cA * a[u] - cB * bv[u] - cC * cv[u];
-          qout[base + e] = q;
-        }
-        const int r = e / nx;
-        slab[r * (M + 1) + (e - r * nx)] = (T)q;
-      }
-    }
-  }
-  __syncthreads();
-  slab_dst<T, L, WG, true>(slab, nx, exch, reinterpret_cast<const C*>(P.twx));
-  slab_dst<T, L, WG, false>(slab, M, exch, reinterpret_cast<const C*>(P.twy));
-  T* out = reinterpret_cast<T*>(P.scratch) + (size_t)b * P.NS + (size_t)lvl * P.ms;
-  for (int e = threadIdx.x; e < nx * M; e += WG) {
-    const int r = e / M;
-    out[e] = slab[r * (M + 1) + (e - r * M)];
-  }
+  if ((check || mode == FWD_LANCZOS) && P.st[blockIdx.y].state != ST_RUNNING) return;
+  dst2_fwd_tile<T, L, WG>(P, mode, in, blockIdx.y, blockIdx.x);
 }
 
 // last pass, fused: DST-I along y and x of one level of the scratch, FP64 rows out,
-// with the block's partial of <q, p> in MINRES modes (one partial per level).  Modes
+// with the block's partial of <q, p> in the GAMMA modes (one partial per level).  Modes
 // as in k_dstx_inv.
 template <typename T, int L, int WG>
 __global__ void __launch_bounds__(WG)
 k_dst2_inv(DevPlan P, int mode, double* __restrict__ outp) {
-  using C = cplx<T>;
-  constexpr int M = L / 2;
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* slab = reinterpret_cast<T*>(smem);
-  C* exch = reinterpret_cast<C*>(smem + slab_bytes<T, L>());
-  const int b = blockIdx.y, lvl = blockIdx.x;
-  const size_t off = (size_t)b * P.N;
-  double* out = outp ? outp + off : nullptr;
-  const double* q = nullptr;
-  const MinresState* st = P.st + b;
-  if (mode != INV_PLAIN) {
-    if (st->state != ST_RUNNING) return;
-    if (mode == INV_GAMMA_INIT || mode == INV_Z_INIT) {
-      out = P.Z[zslot(1)] + off;
-      if (mode == INV_GAMMA_INIT) q = P.V[1] + off;
-    } else {
-      const int jj = st->iter + 1;
-      out = P.Z[zslot(jj + 1)] + off;
-      if (mode == INV_GAMMA_ITER) q = P.V[(jj + 1) % 3] + off;
-    }
-  }
-  const int nx = M - 1, cnt = nx * M;
-  const T* scr = reinterpret_cast<const T*>(P.scratch) + (size_t)b * P.NS + (size_t)lvl * P.ms;
-  constexpr int BATCH = 16;
-  for (int e0 = 0; e0 < cnt; e0 += BATCH * WG) {
-    T v[BATCH];
-#pragma unroll
-    for (int u = 0; u < BATCH; ++u) v[u] = scr[min(e0 + (int)threadIdx.x + u * WG, cnt - 1)];
-#pragma unroll
-    for (int u = 0; u < BATCH; ++u) {
-      const int e = e0 + (int)threadIdx.x + u * WG;
-      if (e < cnt) {
-        const int r = e / M;
-        slab[r * (M + 1) + (e - r * M)] = v[u];
-      }
-    }
-  }
-  __syncthreads();
-  slab_dst<T, L, WG, false>(slab, M, exch, reinterpret_cast<const C*>(P.twy));
-  slab_dst<T, L, WG, true>(slab, nx, exch, reinterpret_cast<const C*>(P.twx));
-  const size_t base = (size_t)lvl * P.m;
-  double* o = out + base;
-  const double* qq = q ? q + base : nullptr;
-  const int total = nx * nx;
-  double acc = 0.0;
-  for (int e0 = 0; e0 < total; e0 += BATCH * WG) {
-    double qv[BATCH];
-    if (qq) {
-#pragma unroll
-      for (int u = 0; u < BATCH; ++u) qv[u] = qq[min(e0 + (int)threadIdx.x + u * WG, total - 1)];
-    }
-#pragma unroll
-    for (int u = 0; u < BATCH; ++u) {
-      const int e = e0 + (int)threadIdx.x + u * WG;
-      if (e < total) {
-        const int r = e / nx;
-        const double val = (double)slab[r * (M + 1) + (e - r * nx)];
-        o[e] = val;
-        if (qq) acc += val * qv[u];
-      }
-    }
-  }
+  const int b = blockIdx.y;
+  if (mode != INV_PLAIN && P.st[b].state != ST_RUNNING) return;
+  const double acc = dst2_inv_tile<T, L, WG>(P, mode, outp, b, blockIdx.x);
   if (mode != INV_GAMMA_INIT && mode != INV_GAMMA_ITER) return;
   const double bs = block_sum(acc);
-  if (threadIdx.x == 0) part_slot(P, PART_GAMMA, b)[lvl] = bs;
+  if (threadIdx.x == 0) part_slot(P, PART_GAMMA, b)[blockIdx.x] = bs;
 }
 
 // ---------------------------------------------------------------------------
@@ -512,6 +319,10 @@ int slab_wg(int nx, int ny, int prec, int maxlds, size_t margin) {
     if (lds && lds + margin <= (size_t)maxlds) return wg;
   }
   return 0;
+}
+
+size_t slab_lds_bytes(int L, int wg, int prec) {
+  return prec == 1 ? slab_lds_t<float>(L, wg) : slab_lds_t<double>(L, wg);
 }
 
 bool transform_tile_valid(int kind, int L, int wg, int prec) {

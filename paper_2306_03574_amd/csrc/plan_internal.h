@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <string>
 #include <vector>
 
 #include "../../include/abac.h"
@@ -59,4 +60,6 @@ abac_status plan_peek_snapshot(abac_plan* p, long long seq, int* ready, const Mi
 long long plan_snapshots_posted(const abac_plan* p);
 hipError_t launch_fill_normal(double* out, unsigned long long n, unsigned long long seed, hipStream_t s);
 hipError_t launch_fill_zero(double* out, unsigned long long n, hipStream_t s);
+// the thread-local message abac_last_error() returns
+void set_last_error(const std::string& msg);
 }  // namespace abac
