@@ -367,7 +367,7 @@ def run_serving(args):
     out = None
     trace = synth.serving_trace(args.rate, args.requests, seed=5)
     results, wall = run_trace(trace, budget, max_active=args.max_active, prec=prec, tol=args.tol, maxit=args.maxit,
-                              progress=log, warm_classes=classes)
+                              progress=log, warm_classes=classes, group_max_unknowns=args.group_lane)
     lat = np.array([r["latency"] for r in results]) * 1e3
     ok = sum(1 for r in results if r["status"] == 0 and r["relres"] <= args.tol)
     per_class = {}
@@ -381,7 +381,7 @@ def run_serving(args):
         if prec == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": "serving_mix", "rate_per_s": args.rate, "requests": len(results),
                    "budget_gb": args.budget_gb, "max_active": args.max_active, "tol": args.tol,
-                   "precond_precision": prec},
+                   "precond_precision": prec, "group_lane_max_unknowns": args.group_lane},
         "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
         "converged": ok,
         "per_class_p50_p99_ms": {k: [round(float(np.percentile(v, 50)), 2), round(float(np.percentile(v, 99)), 2),
@@ -407,6 +407,9 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="serving: requests in the trace")
     ap.add_argument("--budget-gb", type=float, default=160.0, help="serving: HBM budget")
     ap.add_argument("--max-active", type=int, default=16, help="serving: concurrent solves")
+    ap.add_argument("--group-lane", type=int, default=0,
+                    help="serving: requests with at most this many unknowns advance together in one group "
+                         "(one launch per MINRES step for all of them); 0 = off")
     ap.add_argument("--copy-probe", action="store_true", help="only run the HBM counter calibration copy")
     ap.add_argument("--copy-gib", type=float, default=None, help="copy probe: buffer size in GiB (default 1)")
     ap.add_argument("--solver", default="minres", choices=["minres", "gmres"],

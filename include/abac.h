@@ -222,8 +222,9 @@ abac_status abac_group_destroy(abac_group *group);
  * transform lengths must have 256-thread tiles (1D grids up to nx = 2047).  The
  * group's stream waits for each member's stream (its set-up).  The plans' state is
  * copied: a member must not be changed (abac_plan_set_coefficient, abac_plan_set_tiles)
- * or advanced on its own while it is in the group.  ABAC_EINVAL otherwise.
- * Synchronises the group's stream (the previous members' work). */
+ * or advanced on its own while it is in the group.  ABAC_EINVAL otherwise.  The new
+ * membership takes effect in stream order: launches already enqueued keep the old one.
+ * A member that leaves must be finished (abac_minres_finish) before it is changed. */
 abac_status abac_group_set(abac_group *group, abac_plan *const *plans, int n);
 
 /* Enqueue `iterations` MINRES iterations of every member (members that have stopped
@@ -289,6 +290,15 @@ typedef struct abac_server abac_server;
 
 abac_status abac_server_create(size_t budget_bytes, int max_active, abac_server **out);
 abac_status abac_server_destroy(abac_server *server);
+
+/* Group lane: requests whose right-hand side has at most max_unknowns unknowns (and
+ * whose grid a group accepts, see abac_group_set) run as members of one group on a
+ * stream of the server's own, so a step advances all of them with one launch per
+ * MINRES step; the others keep their own streams.  0 (the default) turns the lane off.
+ * Lane members do not count against max_active (the lane holds up to 64 of them).
+ * Only while the server is idle (no request queued or active): ABAC_EINVAL otherwise.
+ * Results are the same either way (bitwise). */
+abac_status abac_server_group_lane(abac_server *server, size_t max_unknowns);
 
 /* Queue a solve of grid (nx, ny, nt), final time T, alpha, preconditioner precision
  * prec, to relative residual tol within maxit iterations.  arrival_s is the arrival

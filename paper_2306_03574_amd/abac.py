@@ -28,7 +28,7 @@ EXPORTED = [
     "abac_server_submit", "abac_server_step", "abac_server_result", "abac_server_clock",
     "abac_server_bytes_in_use", "abac_plan_tiles", "abac_plan_set_coefficient", "abac_apply_T", "abac_apply_Cinv",
     "abac_gmres_solve", "abac_plan_set_tiles", "abac_apply_Pinv_noalloc", "abac_group_create",
-    "abac_group_destroy", "abac_group_set", "abac_group_advance",
+    "abac_group_destroy", "abac_group_set", "abac_group_advance", "abac_server_group_lane",
 ]
 
 _lib = None
@@ -109,6 +109,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abac_plan_set_coefficient.restype = I
     lib.abac_apply_Pinv_noalloc.argtypes = [I, I, I, D, D, I, I, VP, VP, VP]
     lib.abac_apply_Pinv_noalloc.restype = I
+    lib.abac_server_group_lane.argtypes = [P, SZ]
+    lib.abac_server_group_lane.restype = I
     lib.abac_group_create.argtypes = [VP, ctypes.POINTER(P)]
     lib.abac_group_create.restype = I
     lib.abac_group_destroy.argtypes = [P]

@@ -231,11 +231,15 @@ __global__ void __launch_bounds__(kGroupWG) k_group_xinv(const GroupTable* __res
 
 using namespace abac;
 
+constexpr int kGroupStage = 4;   // pinned host copies of the table, used in turn
+
 struct abac_group {
   hipStream_t stream;
   int prec;
-  GroupTable* d_table;           // device copy
-  std::vector<GroupTable> h;     // host copy (one element)
+  GroupTable* d_table;                 // the table the launches read
+  GroupTable* h_stage[kGroupStage];    // pinned host copies, uploaded in stream order
+  hipEvent_t stage_ev[kGroupStage];    // upload of each copy complete
+  int stage_next;
   std::vector<abac_plan*> members;
   int blocks[GS_COUNT];
   size_t lds[GS_COUNT];
@@ -335,6 +339,15 @@ abac_status group_release(abac_group* g) {
 
 }  // namespace
 
+namespace abac {
+bool group_accepts(const abac_plan* p) {
+  if (!p || p->prec == ABAC_PREC_NONE || p->P.small) return false;
+  int blocks[GS_COUNT];
+  size_t lds[GS_COUNT];
+  return member_shape(p->P, p->prec, blocks, lds);
+}
+}  // namespace abac
+
 extern "C" {
 
 abac_status abac_group_create(void* stream, abac_group** out) {
@@ -343,16 +356,24 @@ abac_status abac_group_create(void* stream, abac_group** out) {
   abac_group* g = new abac_group();
   g->stream = static_cast<hipStream_t>(stream);
   g->prec = -1;
-  g->h.resize(1);
-  std::memset(g->h.data(), 0, sizeof(GroupTable));
+  g->d_table = nullptr;
+  g->stage_next = 0;
+  for (int k = 0; k < kGroupStage; ++k) {
+    g->h_stage[k] = nullptr;
+    g->stage_ev[k] = nullptr;
+  }
+  g->joined = g->done = nullptr;
   std::memset(g->blocks, 0, sizeof(g->blocks));
   std::memset(g->lds, 0, sizeof(g->lds));
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&g->d_table), sizeof(GroupTable));
+  for (int k = 0; e == hipSuccess && k < kGroupStage; ++k) {
+    e = hipHostMalloc(reinterpret_cast<void**>(&g->h_stage[k]), sizeof(GroupTable), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&g->stage_ev[k], hipEventDisableTiming);
+  }
   if (e == hipSuccess) e = hipEventCreateWithFlags(&g->joined, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&g->done, hipEventDisableTiming);
   if (e != hipSuccess) {
-    if (g->d_table) (void)hipFree(g->d_table);
-    delete g;
+    abac_group_destroy(g);
     return gfail(ABAC_ENOMEM, std::string("group set-up: ") + hipGetErrorString(e));
   }
   *out = g;
@@ -362,9 +383,13 @@ abac_status abac_group_create(void* stream, abac_group** out) {
 abac_status abac_group_destroy(abac_group* g) {
   if (!g) return ABAC_OK;
   (void)hipStreamSynchronize(g->stream);
-  (void)hipEventDestroy(g->joined);
-  (void)hipEventDestroy(g->done);
-  (void)hipFree(g->d_table);
+  for (int k = 0; k < kGroupStage; ++k) {
+    if (g->stage_ev[k]) (void)hipEventDestroy(g->stage_ev[k]);
+    if (g->h_stage[k]) (void)hipHostFree(g->h_stage[k]);
+  }
+  if (g->joined) (void)hipEventDestroy(g->joined);
+  if (g->done) (void)hipEventDestroy(g->done);
+  if (g->d_table) (void)hipFree(g->d_table);
   delete g;
   return ABAC_OK;
 }
@@ -373,7 +398,10 @@ abac_status abac_group_set(abac_group* g, abac_plan* const* plans, int n) {
   set_last_error("");
   if (!g || (n && !plans)) return gfail(ABAC_EINVAL, "NULL argument");
   if (n < 0 || n > kGroupMax) return gfail(ABAC_EINVAL, "a group holds 0.." + std::to_string(kGroupMax) + " plans");
-  GroupTable& H = g->h[0];
+  // the next pinned copy, once its previous upload has completed
+  const int k = g->stage_next;
+  GHIP(hipEventSynchronize(g->stage_ev[k]));
+  GroupTable& H = *g->h_stage[k];
   std::memset(&H, 0, sizeof(GroupTable));
   int prec = -1;
   int blocks[GS_COUNT], total[GS_COUNT] = {0};
@@ -405,16 +433,17 @@ abac_status abac_group_set(abac_group* g, abac_plan* const* plans, int n) {
     g->lds[k] = lmax[k];
   }
   H.n = n;
-  // the previous table may still be read by enqueued work
-  GHIP(hipStreamSynchronize(g->stream));
-  GHIP(hipMemcpy(g->d_table, &H, sizeof(GroupTable), hipMemcpyHostToDevice));
-  g->members.assign(plans, plans + n);
-  g->prec = prec;
-  // the group's launches follow each member's set-up on its own stream
-  for (abac_plan* p : g->members) {
-    GHIP(hipEventRecord(g->joined, p->stream));
+  // the group's stream waits for each member's stream (its set-up), then takes the new
+  // table in stream order: launches enqueued before read the old one
+  for (int r = 0; r < n; ++r) {
+    GHIP(hipEventRecord(g->joined, plans[r]->stream));
     GHIP(hipStreamWaitEvent(g->stream, g->joined, 0));
   }
+  GHIP(hipMemcpyAsync(g->d_table, &H, sizeof(GroupTable), hipMemcpyHostToDevice, g->stream));
+  GHIP(hipEventRecord(g->stage_ev[k], g->stream));
+  g->stage_next = (k + 1) % kGroupStage;
+  g->members.assign(plans, plans + n);
+  g->prec = prec;
   return ABAC_OK;
 }
 

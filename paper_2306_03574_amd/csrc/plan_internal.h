@@ -62,4 +62,6 @@ hipError_t launch_fill_normal(double* out, unsigned long long n, unsigned long l
 hipError_t launch_fill_zero(double* out, unsigned long long n, hipStream_t s);
 // the thread-local message abac_last_error() returns
 void set_last_error(const std::string& msg);
+// whether a group (abac_group_set) can take the plan as a member (its solve aside)
+bool group_accepts(const abac_plan* p);
 }  // namespace abac

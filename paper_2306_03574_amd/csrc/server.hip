@@ -10,6 +10,12 @@
 // keeping up to kAhead iterations in flight beyond the newest observed state (fewer
 // when the observed residual decay predicts the stop), and retires solves whose
 // snapshot shows that every right-hand side has stopped.
+//
+// Group lane (abac_server_group_lane): requests of at most a given number of unknowns,
+// whose iterations are bound by launch latency, run as members of one group
+// (abac_group_*): a step advances all of them together with one launch per MINRES
+// step, on the server's own stream; requests join and leave the group as they are
+// admitted and retired.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,6 +36,7 @@ namespace {
 
 constexpr int kAhead = 2;
 constexpr double kStarveSeconds = 0.25;
+constexpr int kGroupLaneMax = 64;   // members of the group lane (abac_group_set's limit)
 
 struct Key {
   int nx, ny, nt, prec;
@@ -70,6 +77,7 @@ struct Req {
   bool keep;
   Phase phase = QUEUED;
   Slot* slot = nullptr;
+  bool in_group = false;
   long long enq = 0, obs = 0, est = LLONG_MAX;
   double rel_last = -1.0;
   int iters = 0, status = 0;
@@ -100,6 +108,12 @@ struct abac_server {
   std::vector<Req*> active;
   std::map<long long, Req*> reqs;
   std::vector<Slot*> slots;
+  // group lane
+  size_t group_max_n = 0;       // 0: no lane
+  hipStream_t gstream = nullptr;
+  abac_group* group = nullptr;
+  std::vector<Req*> gmembers;
+  bool gdirty = false;
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -187,14 +201,34 @@ abac_status start(abac_server* s, Req* r) {
   r->est = LLONG_MAX;
   r->rel_last = -1.0;
   r->phase = ACTIVE;
+  r->in_group = s->group && sl->n <= s->group_max_n && (int)s->gmembers.size() < kGroupLaneMax &&
+                (s->gmembers.empty() || s->gmembers[0]->key.prec == sl->key.prec) &&
+                abac::group_accepts(sl->plan);
+  if (r->in_group) {
+    s->gmembers.push_back(r);
+    s->gdirty = true;
+  }
   return ABAC_OK;
 }
 
+// Unknowns of a request's right-hand side.
+size_t req_unknowns(const Key& k) { return (size_t)k.nt * k.nx * (k.ny ? k.ny : 1); }
+
+// Admission: max_active caps the solves on their own streams; requests small enough
+// for the group lane are capped by the lane's size instead (they cost a share of the
+// lane's launches, not launches of their own).
 void admit(abac_server* s) {
   const double t = s->now();
   for (auto it = s->queue.begin(); it != s->queue.end();) {
-    if ((int)s->active.size() >= s->max_active) return;
+    const int own = (int)(s->active.size() - s->gmembers.size());
+    const bool lane_ok = s->group && (int)s->gmembers.size() < kGroupLaneMax;
+    if (own >= s->max_active && !lane_ok) return;
     Req* r = *it;
+    const bool small = s->group && req_unknowns(r->key) <= s->group_max_n;
+    if (small ? !lane_ok : own >= s->max_active) {
+      ++it;
+      continue;
+    }
     abac_status err;
     Slot* sl = acquire_slot(s, r->key, &err);
     if (!sl) {
@@ -225,7 +259,22 @@ void admit(abac_server* s) {
   }
 }
 
-// Advance one active request; returns true when it has finished.
+void finish_req(abac_server* s, Req* r) {
+  int it = 0, stt = 0;
+  double rr = 0;
+  abac_minres_finish(r->slot->plan, &it, &rr, &stt);
+  r->iters = it;
+  r->relres = rr;
+  r->status = stt;
+  r->t_done = s->now();
+}
+
+// Whether a request wants another iteration queued: fewer than kAhead beyond the
+// newest observed state, not past maxit or the predicted stop.
+bool wants_more(const Req* r) { return r->enq < r->maxit && r->enq - r->obs <= kAhead && r->enq < r->est; }
+
+// Advance one active request; returns true when it has finished.  Requests of the group
+// lane are only observed here (the group advances them).
 bool advance(abac_server* s, Req* r) {
   abac_plan* p = r->slot->plan;
   // observe every snapshot that has completed since the last look
@@ -268,7 +317,15 @@ bool advance(abac_server* s, Req* r) {
       return true;
     }
   }
-  if (r->enq < r->maxit && r->enq - r->obs <= kAhead && r->enq < r->est) {
+  if (r->in_group) {
+    if (r->enq >= r->maxit && r->obs >= r->enq) {
+      finish_req(s, r);
+      return true;
+    }
+    if (r->obs >= r->enq && r->enq >= r->est) r->est = r->enq + 1;   // prediction was early
+    return false;
+  }
+  if (wants_more(r)) {
     if (abac_minres_advance(p, 1) == ABAC_OK) ++r->enq;
   } else if (r->enq >= r->maxit && r->obs >= r->enq) {
     int it = 0, stt = 0;
@@ -307,6 +364,8 @@ abac_status abac_server_create(size_t budget_bytes, int max_active, abac_server*
 
 abac_status abac_server_destroy(abac_server* s) {
   if (!s) return ABAC_OK;
+  if (s->group) abac_group_destroy(s->group);
+  if (s->gstream) (void)hipStreamDestroy(s->gstream);
   for (Slot* sl : s->slots)
     if (sl->stream) (void)hipStreamSynchronize(sl->stream);
   while (!s->slots.empty()) free_slot(s, s->slots.back());
@@ -337,12 +396,28 @@ abac_status abac_server_submit(abac_server* s, int nx, int ny, int nt, double T,
   return ABAC_OK;
 }
 
+abac_status abac_server_group_lane(abac_server* s, size_t max_unknowns) {
+  if (!s) return ABAC_EINVAL;
+  if (!s->active.empty() || !s->queue.empty()) return ABAC_EINVAL;   // only while idle
+  if (max_unknowns && !s->group) {
+    if (hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking) != hipSuccess) return ABAC_EDEVICE;
+    abac_status st = abac_group_create(s->gstream, &s->group);
+    if (st != ABAC_OK) return st;
+  }
+  s->group_max_n = max_unknowns;
+  return ABAC_OK;
+}
+
 abac_status abac_server_step(abac_server* s, int* active, int* queued) {
   if (!s) return ABAC_EINVAL;
   admit(s);
   for (size_t i = 0; i < s->active.size();) {
     Req* r = s->active[i];
     if (advance(s, r)) {
+      if (r->in_group) {
+        s->gmembers.erase(std::find(s->gmembers.begin(), s->gmembers.end(), r));
+        s->gdirty = true;
+      }
       r->phase = DONE;
       if (!r->keep) {
         r->slot->busy = false;
@@ -353,6 +428,24 @@ abac_status abac_server_step(abac_server* s, int* active, int* queued) {
       continue;
     }
     ++i;
+  }
+  // the group lane: new membership, then one more iteration of every member if any
+  // of them wants it (members that have stopped skip the work on the device)
+  if (s->group) {
+    if (s->gdirty) {
+      std::vector<abac_plan*> plans;
+      for (Req* r : s->gmembers) plans.push_back(r->slot->plan);
+      abac_status st = abac_group_set(s->group, plans.data(), (int)plans.size());
+      if (st != ABAC_OK) return st;
+      s->gdirty = false;
+    }
+    bool more = false;
+    for (Req* r : s->gmembers) more = more || wants_more(r);
+    if (more) {
+      abac_status st = abac_group_advance(s->group, 1);
+      if (st != ABAC_OK) return st;
+      for (Req* r : s->gmembers) ++r->enq;
+    }
   }
   if (active) *active = (int)s->active.size();
   if (queued) *queued = (int)s->queue.size();

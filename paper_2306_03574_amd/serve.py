@@ -15,11 +15,13 @@ from .abac import load_library, _check, PREC, OK, EAGAIN, AbacError
 
 
 class Server:
-    def __init__(self, budget_bytes: int, max_active: int = 16):
+    def __init__(self, budget_bytes: int, max_active: int = 16, group_max_unknowns: int = 0):
         self._lib = load_library()
         h = ctypes.c_void_p()
         _check(self._lib.abac_server_create(int(budget_bytes), int(max_active), ctypes.byref(h)), "abac_server_create")
         self._h = h
+        if group_max_unknowns:
+            _check(self._lib.abac_server_group_lane(self._h, int(group_max_unknowns)), "abac_server_group_lane")
 
     def clock(self) -> float:
         return float(self._lib.abac_server_clock(self._h))
@@ -88,12 +90,13 @@ class Server:
 
 
 def run_trace(trace, budget_bytes, max_active=16, prec="fp32", tol=1e-8, maxit=500, progress=None,
-              warm_classes=()):
+              warm_classes=(), group_max_unknowns=0):
     """Replay a Poisson trace (list of dicts with arrival, nx, ny, nt, alpha, seed):
     each request is submitted when the server clock reaches its arrival time.
+    group_max_unknowns > 0 runs requests up to that size in the server's group lane.
     Returns (per-request results in trace order, wall seconds from the first arrival
     to the last completion)."""
-    srv = Server(budget_bytes, max_active)
+    srv = Server(budget_bytes, max_active, group_max_unknowns)
     if warm_classes:
         # one untimed solve per shape class: the server keeps their plans and graphs cached
         warm = [srv.submit(nx, ny, nt, a, seed=1, prec=prec, tol=tol, maxit=maxit) for (nx, ny, nt, a) in warm_classes]

@@ -144,3 +144,33 @@ def test_admission_respects_budget_and_queues():
     assert peak_active <= 2
     assert all(r["status"] == 0 and r["relres"] <= 1e-8 for r in out.values())
     srv.close()
+
+
+@pytest.mark.gpu
+def test_group_lane_gives_the_same_results():
+    """The server's group lane (requests of up to 300000 unknowns advance together, one
+    launch per MINRES step) returns bitwise the solutions, counts and residuals of the
+    server without it, for a mix of shapes submitted together and while others run."""
+    from paper_2306_03574_amd.serve import Server
+    mix = [(255, 0, 64, 1e-2), (1023, 0, 256, 1e-3), (63, 63, 64, 1e-2), (255, 0, 1024, 1e-3), (4095, 0, 64, 1e-3),
+           (63, 63, 256, 1e-3), (127, 127, 64, 1e-3), (1023, 0, 64, 1e-2)]
+    out = {}
+    for lane in (0, 300_000):
+        print(f"[case] server group lane {lane}", flush=True)
+        srv = Server(64 << 30, 16, lane)
+        first = [srv.submit(nx, ny, nt, a, seed=5100 + i, keep=True) for i, (nx, ny, nt, a) in enumerate(mix[:4])]
+        for _ in range(3):
+            srv.step()
+        later = [srv.submit(nx, ny, nt, a, seed=5104 + i, keep=True) for i, (nx, ny, nt, a) in enumerate(mix[4:])]
+        tickets = first + later
+        sizes = {t: nt * nx * max(ny, 1) for t, (nx, ny, nt, a) in zip(tickets, mix)}
+        res = srv.drain(tickets, n_unknowns=sizes, timeout=120)
+        out[lane] = [res[t] for t in tickets]
+        srv.close()
+    for a, b, shape in zip(out[0], out[300_000], mix):
+        assert a["status"] == b["status"] == 0 and a["relres"] <= 1e-8, shape
+        assert a["iters"] == b["iters"] and a["relres"] == b["relres"], shape
+        assert np.array_equal(a["u"], b["u"]), shape
+    # one lane member against the oracle (FP32 transforms: count within 2)
+    ref = _oracle_solve(255, 0, 64, 1e-2, 5100)
+    assert abs(out[300_000][0]["iters"] - ref.iters) <= 2
