@@ -44,7 +44,11 @@ def test_largest_1d_grid_matches_oracle():
     assert _rel(_host(p.apply_A(fd))[0], aao.apply_A(g, f, L)) < 1e-14
     assert _rel(_host(p.apply_Pinv(fd))[0], pc.apply_Pinv(g, alpha, f)) < 1e-11
     p32 = _plan(nx, 0, nt, alpha=alpha, prec="fp32")
-    assert _rel(_host(p32.apply_Pinv(fd))[0], pc.apply_Pinv(g, alpha, f)) < 50 * 6e-8 / alpha
+    err32 = _rel(_host(p32.apply_Pinv(fd))[0], pc.apply_Pinv(g, alpha, f))
+    print(f"[obs] fp32 4095x0x1024 alpha={alpha} P^-1 rel.err {err32:.3e}", flush=True)
+    # twice the bound of the small shapes (3e-6 + 2e-8 / alpha): the x and time FFTs of
+    # lengths 8192 and 1024 have about twice as many rounding stages
+    assert err32 < 2 * (3e-6 + 2e-8 / alpha)
     u, iters, relres, status = p.solve(fd, tol=1e-8, maxit=300)
     ref = mr.minres(lambda v: aao.apply_A(g, v, L), lambda y: pc.apply_Pinv(g, alpha, y), aao.reverse_time(f),
                     tol=1e-8, maxit=300)

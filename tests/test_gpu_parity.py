@@ -71,7 +71,9 @@ def test_apply_Pinv_fp64(nx, ny, nt, alpha):
 @pytest.mark.parametrize("nx,ny,nt", [(15, 0, 16), (63, 0, 64), (31, 31, 32), (15, 7, 16)])
 @pytest.mark.parametrize("alpha", [1e-1, 1e-2, 1e-3])
 def test_apply_Pinv_fp32(nx, ny, nt, alpha):
-    """FP32 transforms: error ~ eps32 / alpha (the D_alpha^{-1} amplification)."""
+    """FP32 transforms: error ~ eps32 / alpha (the D_alpha^{-1} amplification).  Measured
+    on these shapes: up to 1.1e-5 at alpha = 1e-3, 1.9e-6 at 1e-2, 5.4e-7 at 1e-1; the
+    bound 3e-6 + 2e-8 / alpha sits 2 to 6 times above that."""
     g = Grid(nx, ny, nt, T=1.0)
     r = np.random.default_rng(13).standard_normal(g.shape)
     p = _plan(nx, ny, nt, alpha=alpha, prec="fp32")
@@ -79,7 +81,7 @@ def test_apply_Pinv_fp32(nx, ny, nt, alpha):
     ref = pc.apply_Pinv(g, alpha, r)
     err = _rel(z, ref)
     print(f"[obs] fp32 {nx}x{ny}x{nt} alpha={alpha} P^-1 rel.err {err:.3e}", flush=True)
-    assert err < 50 * 6e-8 / alpha
+    assert err < 3e-6 + 2e-8 / alpha
 
 
 def test_apply_Pinv_alpha_one_matches_dense():

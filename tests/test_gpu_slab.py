@@ -80,7 +80,8 @@ def test_fused_Pinv_fp64_matches_oracle(n, nt, alpha, monkeypatch):
 
 @pytest.mark.parametrize("alpha", [1e-2, 1e-3])
 def test_fused_Pinv_fp32_127_matches_oracle(alpha, monkeypatch):
-    """127 x 127 level in FP32 (the batched 127^2 x 128 workload's shape), error ~ eps32 / alpha."""
+    """127 x 127 level in FP32 (the batched 127^2 x 128 workload's shape), error ~ eps32 / alpha
+    (measured 7.7e-6 at alpha = 1e-3, 1.4e-6 at 1e-2; bound 3e-6 + 2e-8 / alpha)."""
     n, nt = 127, 8
     g = Grid(n, n, nt, T=1.0)
     r = np.random.default_rng(33).standard_normal(g.shape)
@@ -89,7 +90,7 @@ def test_fused_Pinv_fp32_127_matches_oracle(alpha, monkeypatch):
     z = _host(p.apply_Pinv(_dev(r[None])))[0]
     err = _rel(z, pc.apply_Pinv(g, alpha, r))
     print(f"[obs] fused fp32 127^2 alpha={alpha} P^-1 rel.err {err:.3e}", flush=True)
-    assert err < 50 * 6e-8 / alpha
+    assert err < 3e-6 + 2e-8 / alpha
 
 
 def test_fused_fixed_iterates_and_batch(monkeypatch):
