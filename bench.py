@@ -156,23 +156,32 @@ def source_sha():
 COPY_PROBE_BYTES = 1 << 30
 
 
-def copy_probe(nbytes=None):
+def copy_probe(nbytes=None, pattern="copy"):
     """A plain device copy of COPY_PROBE_BYTES (read and written once per dispatch):
     the calibration run for the HBM byte counters.  Prints its own bandwidth.  Another
-    size (nbytes) gives the copy ceiling at that size."""
+    size (nbytes) gives the copy ceiling at that size.  pattern "half" instead reads the
+    first 64 bytes of every 128-byte line of the buffer into a packed half-size buffer
+    (a second access pattern for the counters: half-line reads at a 128-byte stride)."""
     import torch
     nbytes = nbytes or COPY_PROBE_BYTES
     a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
-    b = torch.empty_like(a)
-    b.copy_(a)
+    if pattern == "half":
+        src = a.view(-1, 16)[:, :8]
+        moved = (nbytes // 2, nbytes // 2)
+    else:
+        src = a
+        moved = (nbytes, nbytes)
+    b = torch.empty(src.shape, dtype=src.dtype, device=src.device)
+    b.copy_(src)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     n = 5
     for _ in range(n):
-        b.copy_(a)
+        b.copy_(src)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / n
-    print(json.dumps({"copy_bytes": nbytes, "GB/s": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
+    print(json.dumps({"copy_bytes": nbytes, "pattern": pattern, "read_bytes": moved[0], "write_bytes": moved[1],
+                      "GB/s": round((moved[0] + moved[1]) / dt / 1e9, 1)}), flush=True)
 
 
 def run_gpu(w, prec, steps, warmup, tol, maxit, profile=True, solver="minres", restart=15):
@@ -412,13 +421,15 @@ def main():
                          "(one launch per MINRES step for all of them); 0 = off")
     ap.add_argument("--copy-probe", action="store_true", help="only run the HBM counter calibration copy")
     ap.add_argument("--copy-gib", type=float, default=None, help="copy probe: buffer size in GiB (default 1)")
+    ap.add_argument("--copy-pattern", default="copy", choices=["copy", "half"],
+                    help="copy probe: a plain copy, or half-line reads at a 128-byte stride")
     ap.add_argument("--solver", default="minres", choices=["minres", "gmres"],
                     help="minres: Y T u = Y f with the ABAC preconditioner (the method); gmres: T u = f "
                          "right-preconditioned by the block alpha-circulant C_alpha")
     ap.add_argument("--restart", type=int, default=15, help="gmres: restart length (<= 15)")
     args = ap.parse_args()
     if args.copy_probe:
-        copy_probe(int(args.copy_gib * (1 << 30)) // 8 * 8 if args.copy_gib else None)
+        copy_probe(int(args.copy_gib * (1 << 30)) // 128 * 128 if args.copy_gib else None, args.copy_pattern)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single GPU and sharding one solve over "

@@ -3,6 +3,8 @@
     python -m paper_2306_03574_amd.profiling trace <trace_dir> <out.md> --command "..."
     python -m paper_2306_03574_amd.profiling sq <run_dir> [<run_dir> ...] --out <out.md> --kernels REGEX
             --command "..." [--command ...] [--note "..."]
+    python -m paper_2306_03574_amd.profiling requests <lib_run_dir> --probe NAME=RUN_DIR=USEFUL_BYTES ... --out <out.md>
+            --command "..." [--command ...]
     python -m paper_2306_03574_amd.profiling pmc <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir>
             --copy-bytes B --workload NAME --prec fp64|fp32 --out-dir profiles --command "..." [--command ...]
 
@@ -161,6 +163,33 @@ def summarize_pmc(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_byt
     return by_class
 
 
+def _derived(m):
+    """Memory-side figures of one kernel's median counters (those present):
+    * wait share: SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES, the part of the waves' lifetime spent
+      waiting for a dependency (both in quad-cycles);
+    * VMEM level: SQ_INST_LEVEL_VMEM per VMEM instruction (accumulated in-flight count over
+      instructions issued: the mean time an instruction is in flight, in the counter's units);
+    * L1 requests to L2 per wave load: TCP_TCC_READ_REQ_sum / SQ_INSTS_VMEM_RD;
+    * L1 hit share: 1 - TCP_TCC_READ_REQ_sum / TCP_TOTAL_CACHE_ACCESSES_sum (reads dominate);
+    * L2 read latency: TCP_TCC_READ_REQ_LATENCY_sum / TCP_TCC_READ_REQ_sum, in cycles;
+    * L2 hit share: TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum)."""
+    d = []
+    if m.get("SQ_WAIT_INST_ANY") is not None and m.get("SQ_WAVE_CYCLES"):
+        d.append(("wait share", f"{m['SQ_WAIT_INST_ANY'] / m['SQ_WAVE_CYCLES']:.2f}"))
+    vm = (m.get("SQ_INSTS_VMEM_RD") or 0) + (m.get("SQ_INSTS_VMEM_WR") or 0)
+    if m.get("SQ_INST_LEVEL_VMEM") is not None and vm:
+        d.append(("VMEM level per instruction", f"{m['SQ_INST_LEVEL_VMEM'] / vm:.0f}"))
+    if m.get("TCP_TCC_READ_REQ_sum") is not None and m.get("SQ_INSTS_VMEM_RD"):
+        d.append(("L1->L2 read requests per wave load", f"{m['TCP_TCC_READ_REQ_sum'] / m['SQ_INSTS_VMEM_RD']:.2f}"))
+    if m.get("TCP_TCC_READ_REQ_sum") is not None and m.get("TCP_TOTAL_CACHE_ACCESSES_sum"):
+        d.append(("L1 hit share", f"{1 - m['TCP_TCC_READ_REQ_sum'] / m['TCP_TOTAL_CACHE_ACCESSES_sum']:.2f}"))
+    if m.get("TCP_TCC_READ_REQ_LATENCY_sum") is not None and m.get("TCP_TCC_READ_REQ_sum"):
+        d.append(("L2 read latency (cycles)", f"{m['TCP_TCC_READ_REQ_LATENCY_sum'] / m['TCP_TCC_READ_REQ_sum']:.0f}"))
+    if m.get("TCC_HIT_sum") is not None and m.get("TCC_MISS_sum") is not None and m["TCC_HIT_sum"] + m["TCC_MISS_sum"]:
+        d.append(("L2 hit share", f"{m['TCC_HIT_sum'] / (m['TCC_HIT_sum'] + m['TCC_MISS_sum']):.2f}"))
+    return d
+
+
 def summarize_sq(run_dirs, out_md, kernel_regex, commands, note=""):
     """Median per-dispatch SQ counters of the kernels matching `kernel_regex` over the
     dispatches of one or more counter runs (each run may hold different counters), and
@@ -221,13 +250,72 @@ def summarize_sq(run_dirs, out_md, kernel_regex, commands, note=""):
                      f"{waves:.0f} | {per_wave('SQ_INSTS_VALU')} | {per_wave('SQ_INSTS_LDS')} | "
                      f"{per_wave('SQ_INSTS_VMEM_RD')} | {med.get('SQ_LDS_BANK_CONFLICT', float('nan')):.3g} | {busy} |"
                      if waves else f"| `{name}` | {m['wg']} | {m['vgpr']} | {m['scratch']} | {n} | - | - | - | - | - | {busy} |")
-        out[name] = {k: med[k] for k in cols if k in med}
+        out[name] = OrderedDict([(k, med[k]) for k in cols if k in med] +
+                                [(k, v) for k, v in med.items() if k not in cols])
     lines += ["", "Raw medians:", ""]
     for name, d in out.items():
         lines.append(f"* `{name}`: " + ", ".join(f"{k} {v:.4g}" for k, v in d.items()))
+    derived = [(name, _derived(d)) for name, d in out.items()]
+    if any(dv for _, dv in derived):
+        lines += ["", "Derived (where the run holds the counters):", ""]
+        for name, dv in derived:
+            if dv:
+                lines.append(f"* `{name}`: " + "; ".join(f"{k} {v}" for k, v in dv))
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     return out
+
+
+def summarize_requests(lib_dir, probes, out_md, commands, note=""):
+    """The HBM read requests by size (TCC_EA0_RDREQ_{32B,64B,128B}_sum) of the library's
+    kernels and of the calibration probes, and the bytes they give (32, 64 and 128 per
+    request) against the calibrated FETCH_SIZE (2 x its 64-byte count: FETCH_SIZE counts
+    a request as 64 bytes unless TCC_BUBBLE marks it 128).  `probes` maps a probe name
+    to (run_dir, useful_read_bytes_per_dispatch).  Medians over the dispatches that read
+    more than 1000 requests."""
+    import statistics
+
+    def med_by_kernel(run_dir, want=None):
+        path = _one(os.path.join(run_dir, "**", "*counter_collection.csv"))
+        per = OrderedDict()
+        for r in csv.DictReader(open(path)):
+            per.setdefault((short_name(r["Kernel_Name"]), r["Dispatch_Id"]), {})[r["Counter_Name"]] = \
+                float(r["Counter_Value"])
+        agg = OrderedDict()
+        for (k, _), c in per.items():
+            if c.get("TCC_EA0_RDREQ_sum", 0.0) < 1000 or (want and not re.search(want, k)):
+                continue
+            for n, v in c.items():
+                agg.setdefault(k, OrderedDict()).setdefault(n, []).append(v)
+        return OrderedDict((k, ({n: statistics.median(v) for n, v in c.items()}, len(c["TCC_EA0_RDREQ_sum"])))
+                           for k, c in agg.items())
+
+    def row(name, m, n, useful=None):
+        n32, n64 = m.get("TCC_EA0_RDREQ_32B_sum", 0.0), m.get("TCC_EA0_RDREQ_64B_sum", 0.0)
+        n128, tot = m.get("TCC_EA0_RDREQ_128B_sum", 0.0), m["TCC_EA0_RDREQ_sum"]
+        exact = 32 * n32 + 64 * n64 + 128 * n128
+        cal = 2.0 * ((tot - n32) * 64 + n32 * 32)
+        u = f"{useful / 1e6:.1f}" if useful else "-"
+        return (f"| `{name}` | {n} | {tot:.4g} | {n32:.3g} | {n64:.3g} | {n128:.4g} | {exact / 1e6:.1f} | "
+                f"{cal / 1e6:.1f} | {cal / exact:.4f} | {u} |")
+
+    lines = ["# HBM read requests by size: the calibration of the byte counters (rocprofv3 --pmc)", "",
+             "Commands (from the repository root, on one MI355X), one counter set per run:", ""]
+    lines += [f"* `{c}`" for c in commands]
+    if note:
+        lines += ["", note]
+    lines += ["", "| kernel | dispatches | read requests | 32 B | 64 B | 128 B | bytes by request size (MB) | "
+              "2 x FETCH_SIZE (MB) | ratio | useful bytes read (MB) |",
+              "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for pname, (pdir, useful) in probes.items():
+        for k, (m, n) in med_by_kernel(pdir).items():
+            if m["TCC_EA0_RDREQ_sum"] > 1e6:
+                lines.append(row(f"{pname}: {k}", m, n, useful))
+    for k, (m, n) in med_by_kernel(lib_dir, r"^k_").items():
+        lines.append(row(k, m, n))
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return lines
 
 
 def main():
@@ -244,6 +332,12 @@ def main():
     q.add_argument("--kernels", required=True)
     q.add_argument("--command", action="append", required=True)
     q.add_argument("--note", default="")
+    rq = sub.add_parser("requests")
+    rq.add_argument("lib_dir")
+    rq.add_argument("--probe", action="append", default=[], help="name=run_dir=useful_read_bytes")
+    rq.add_argument("--out", required=True)
+    rq.add_argument("--command", action="append", required=True)
+    rq.add_argument("--note", default="")
     p = sub.add_parser("pmc")
     for a in ("fetch_dir", "write_dir", "copy_fetch_dir", "copy_write_dir"):
         p.add_argument(a)
@@ -256,6 +350,14 @@ def main():
     if a.cmd == "sq":
         for name in summarize_sq(a.run_dirs, a.out, a.kernels, a.command, a.note):
             print(name)
+        return
+    if a.cmd == "requests":
+        probes = OrderedDict()
+        for spec in a.probe:
+            name, d, b = spec.split("=")
+            probes[name] = (d, int(b))
+        for line in summarize_requests(a.lib_dir, probes, a.out, a.command, a.note):
+            print(line)
         return
     if a.cmd == "trace":
         for r in summarize_trace(a.trace_dir, a.out_md, a.command, a.note):
