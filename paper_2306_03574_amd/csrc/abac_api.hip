@@ -105,14 +105,15 @@ abac_status describe(int nx, int ny, int nt, double T, double alpha, int prec, i
     P.cy = 0.5 * tau * tau / (hy * hy);
     P.c0 += 2.0 * P.cy;
   }
-  // matvec time chunk: the longest of 32/16/8 levels that still gives >= 2048 blocks
-  // (a fixed rule per shape, since the chunk also fixes the grouping of <A z, z>)
-  // matvec blocks march over st_chunk levels (and their mirrors); longer marches
-  // re-read fewer warm-up levels, shorter ones give more blocks.  The rule depends on
-  // the shape only (not on the batch), so a batched solve sums its partials in the
-  // same order as a single one.
-  P.st_threads = std::min(kStencilThreads, (nx + 63) / 64 * 64);
-  P.st_chunk = 32;
+  // matvec decomposition: two columns per thread and bands of 2 rows; blocks march
+  // over st_chunk levels (and their mirrors).  Longer marches re-read fewer warm-up
+  // levels, shorter ones give more blocks: the chunk is the longest of 64/32/16/8
+  // levels that still gives >= 512 blocks.  The rule depends on the shape only (not on
+  // the batch), so a batched solve sums its partials in the same order as a single one.
+  P.st_cols = nx >= 2 ? 2 : 1;
+  P.st_rows = ny && nx >= 2 ? 2 : 1;
+  P.st_threads = std::min(kStencilThreads, ((nx + P.st_cols - 1) / P.st_cols + 63) / 64 * 64);
+  P.st_chunk = 64;
   while (P.st_chunk > 8 && stencil_blocks(P) < 512) P.st_chunk /= 2;
   P.maxparts = std::max(std::max(stencil_blocks(P), update_blocks(P)), std::max((P.nt * P.ny1 + 1) / 2, P.ms / 2));
   P.maxparts = (P.maxparts + 63) & ~63;

@@ -124,7 +124,9 @@ struct DevPlan {
   int wg_s;            // fused 2D passes (0: separate x and y passes)
   int small;           // 1: one workgroup per right-hand side runs a whole iteration
   int st_chunk;        // forward time levels per matvec block
-  int st_threads;      // columns (threads) per matvec block
+  int st_threads;      // threads per matvec block
+  int st_cols;         // columns per matvec thread (2, or 1 for a one-column grid)
+  int st_rows;         // grid rows per matvec block (1 in 1D)
   int gamma_nparts;    // partial sums of <q, P^{-1} q> per right-hand side
   int prec;            // 0 FP64 transforms, 1 FP32 transforms, 2 no preconditioner
 };
@@ -201,14 +203,12 @@ enum FinKind : int {
   FIN_FINAL = 7    // end of a solve: form u if it is stale
 };
 
-// matvec decomposition: a block covers a band of kStencilRows grid rows (one row in 1D)
-// times st_threads columns (64 <= st_threads <= 256), and st_chunk forward time levels
-// (plus their mirrors)
+// matvec decomposition: a block covers a band of st_rows grid rows times
+// st_threads * st_cols columns, and st_chunk forward time levels (plus their mirrors)
 constexpr int kStencilThreads = 256;
-constexpr int kStencilRows = 4;
 __host__ __device__ inline int stencil_blocks(const DevPlan& P) {
-  const int rb = P.ny ? kStencilRows : 1;
-  const int tiles = ((P.ny1 + rb - 1) / rb) * ((P.nx + P.st_threads - 1) / P.st_threads);
+  const int cols = P.st_threads * P.st_cols;
+  const int tiles = ((P.ny1 + P.st_rows - 1) / P.st_rows) * ((P.nx + cols - 1) / cols);
   const int nchunks = (P.nt / 2 + P.st_chunk - 1) / P.st_chunk;
   return tiles * nchunks;
 }
