@@ -108,13 +108,14 @@ abac_status describe(int nx, int ny, int nt, double T, double alpha, int prec, i
   // matvec decomposition: two columns per thread and bands of 2 rows; blocks march
   // over st_chunk levels (and their mirrors).  Longer marches re-read fewer warm-up
   // levels, shorter ones give more blocks: the chunk is the longest of 64/32/16/8
-  // levels that still gives >= 512 blocks.  The rule depends on the shape only (not on
-  // the batch), so a batched solve sums its partials in the same order as a single one.
+  // levels whose blocks still fill the GPU once at the matvec's occupancy (2 waves on
+  // each of the 1024 SIMDs).  The rule depends on the shape only (not on the batch), so
+  // a batched solve sums its partials in the same order as a single one.
   P.st_cols = nx >= 2 ? 2 : 1;
   P.st_rows = ny && nx >= 2 ? 2 : 1;
   P.st_threads = std::min(kStencilThreads, ((nx + P.st_cols - 1) / P.st_cols + 63) / 64 * 64);
   P.st_chunk = 64;
-  while (P.st_chunk > 8 && stencil_blocks(P) < 512) P.st_chunk /= 2;
+  while (P.st_chunk > 8 && (long long)stencil_blocks(P) * (P.st_threads / 64) < kStencilWaves) P.st_chunk /= 2;
   P.maxparts = std::max(std::max(stencil_blocks(P), update_blocks(P)), std::max((P.nt * P.ny1 + 1) / 2, P.ms / 2));
   P.maxparts = (P.maxparts + 63) & ~63;
   P.prec = prec;

@@ -206,6 +206,7 @@ enum FinKind : int {
 // matvec decomposition: a block covers a band of st_rows grid rows times
 // st_threads * st_cols columns, and st_chunk forward time levels (plus their mirrors)
 constexpr int kStencilThreads = 256;
+constexpr int kStencilWaves = 2048;   // 2 waves per SIMD on 256 CUs x 4 SIMDs
 __host__ __device__ inline int stencil_blocks(const DevPlan& P) {
   const int cols = P.st_threads * P.st_cols;
   const int tiles = ((P.ny1 + P.st_rows - 1) / P.st_rows) * ((P.nx + cols - 1) / cols);
