@@ -1,6 +1,8 @@
 """Build the HIP library ``libabac.so`` for gfx950 in-tree (next to this file).
 
-Usage: ``python -m paper_2306_03574_amd.build`` (or ``build()`` from Python).
+Usage: ``python -m paper_2306_03574_amd.build`` (or ``build()`` from Python);
+``--host-driver`` also builds the C-ABI driver whose host code runs under
+AddressSanitizer (``build_host_driver()``).
 """
 from __future__ import annotations
 
@@ -66,5 +68,46 @@ def build(verbose: bool = False, csrc: str = CSRC, lib: str = LIB) -> str:
     return lib
 
 
+HOST_DRIVER = os.path.join(HERE, "abac_host_driver")
+HOST_DRIVER_SRC = os.path.join(os.path.dirname(HERE), "tests", "host_asan", "abac_host_driver.cpp")
+# AddressSanitizer for the host code only (device code stays uninstrumented)
+HOST_ASAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_host_driver(verbose: bool = False, csrc: str = CSRC, out: str = HOST_DRIVER) -> str:
+    """Compile the C-ABI driver of tests/host_asan together with every library source
+    into one executable whose host code runs under AddressSanitizer (always rebuilds).
+    The translation units compile in parallel, then link."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+
+    cc = hipcc()
+    flags = [f for f in HIPCC_FLAGS if f not in ("-shared", "-fPIC")] + HOST_ASAN_FLAGS
+    srcs = [os.path.join(csrc, s) for s in SOURCES] + [HOST_DRIVER_SRC]
+    with tempfile.TemporaryDirectory(prefix="abac_asan_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.splitext(os.path.basename(s))[0] + ".o") for s in srcs]
+        cmds = [[cc] + flags + ["-c", s, "-o", o] for s, o in zip(srcs, objs)]
+        jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            results = list(ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds))
+        for c, res in zip(cmds, results):
+            if verbose:
+                print(" ".join(c), flush=True)
+            if res.returncode != 0:
+                sys.stderr.write(res.stdout + res.stderr)
+                raise RuntimeError(f"hipcc failed compiling {c[-3]}")
+        link = [cc, "--offload-arch=gfx950"] + HOST_ASAN_FLAGS + objs + ["-o", out + ".tmp"]
+        if verbose:
+            print(" ".join(link), flush=True)
+        res = subprocess.run(link, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking the host driver")
+        os.replace(out + ".tmp", out)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    if "--host-driver" in sys.argv:
+        print(build_host_driver(verbose=True))
