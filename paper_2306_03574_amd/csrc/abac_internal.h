@@ -205,6 +205,10 @@ enum FinKind : int {
 
 // matvec decomposition: a block covers a band of st_rows grid rows times
 // st_threads * st_cols columns, and st_chunk forward time levels (plus their mirrors)
+// two doubles moved by one 16-byte access; 8-byte alignment suffices on gfx950 (rows of
+// odd length start at odd 8-byte offsets)
+typedef double dpair __attribute__((ext_vector_type(2), aligned(8)));
+
 constexpr int kStencilThreads = 256;
 constexpr int kStencilWaves = 2048;   // 2 waves per SIMD on 256 CUs x 4 SIMDs
 __host__ __device__ inline int stencil_blocks(const DevPlan& P) {

@@ -205,8 +205,6 @@ __device__ __forceinline__ double stencil_tile(const DevPlan& P, const double* _
 // load stays inside its row; a clamped pair only ever stands in for a value whose weight
 // is zero or for a column that is not written.  The per-point arithmetic is that of
 // stencil_tile, term for term.
-typedef double dpair __attribute__((ext_vector_type(2), aligned(8)));
-
 // centre values (columns c, c+1) of the RB+2 rows and the outer neighbours (c-1, c+2)
 // of the RB band rows at one level
 template <int RB>

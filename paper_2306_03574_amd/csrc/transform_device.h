@@ -188,19 +188,14 @@ __device__ __forceinline__ void dstx_fwd_tile(const DevPlan& P, int mode, const 
   const int ra = 2 * s, rb = 2 * s + 1;
   const bool va = ra < nrows, vb = rb < nrows;
   C v[R];
+  // odd extension of both rows, without branches (as in the inverse pass)
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const int t = j + i * TPS;
-    T a = 0, c = 0;
-    if (t > 0 && t < Mx) {
-      if (va) a = stage[ra * nx + t - 1];
-      if (vb) c = stage[rb * nx + t - 1];
-    } else if (t > Mx) {
-      const int idx = 2 * Mx - t - 1;
-      if (va) a = -stage[ra * nx + idx];
-      if (vb) c = -stage[rb * nx + idx];
-    }
-    v[i] = C{a, c};
+    const int src = t < Mx ? max(t - 1, 0) : min(2 * Mx - t - 1, Mx - 2);
+    const T a = stage[ra * nx + src], c = stage[rb * nx + src];
+    const bool zero = t == 0 || t == Mx, neg = t > Mx;
+    v[i] = C{zero || !va ? (T)0 : (neg ? -a : a), zero || !vb ? (T)0 : (neg ? -c : c)};
   }
   __syncthreads();
   fft_seq<T, L, false>(v, j, lds + s, S, tw);
@@ -539,39 +534,46 @@ __device__ __forceinline__ double dstx_inv_tile(const DevPlan& P, int mode, doub
   const int ra = 2 * s, rb = 2 * s + 1;
   const bool va = ra < nrows, vb = rb < nrows;
   C v[R];
+  // odd extension of both rows, without branches: element t is x[t-1] for 0 < t < Mx,
+  // -x[2 Mx - t - 1] for t > Mx, 0 at t = 0 and t = Mx (rows past the tile read stale
+  // LDS words of the staging area, selected away)
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const int t = j + i * TPS;
-    T a = 0, c = 0;
-    if (t > 0 && t < Mx) {
-      if (va) a = stage[ra * Mx + t - 1];
-      if (vb) c = stage[rb * Mx + t - 1];
-    } else if (t > Mx) {
-      const int idx = 2 * Mx - t - 1;
-      if (va) a = -stage[ra * Mx + idx];
-      if (vb) c = -stage[rb * Mx + idx];
-    }
-    v[i] = C{a, c};
+    const int src = t < Mx ? max(t - 1, 0) : min(2 * Mx - t - 1, Mx - 2);
+    const T a = stage[ra * Mx + src], c = stage[rb * Mx + src];
+    const bool zero = t == 0 || t == Mx, neg = t > Mx;
+    v[i] = C{zero || !va ? (T)0 : (neg ? -a : a), zero || !vb ? (T)0 : (neg ? -c : c)};
   }
   __syncthreads();
   fft_seq<T, L, false>(v, j, lds + s, S, tw);
   const double scl = 1.0 / sqrt((double)L);
-  // stage the FP64 rows ([2S][nx+2] padded: odd stride in 8-byte words) and write
-  // them out contiguously; with q, accumulate <q, p> in a fixed order for a fixed tile
+  // stage the FP64 rows and write them out contiguously; with q, accumulate <q, p> in a
+  // fixed order for a fixed tile.  Rows are [2S][nx+2] (odd stride in 8-byte words, so
+  // the sequences of a wave write different banks), or packed [2][nx] with one sequence
+  // per block, where the block's output is then one contiguous run.
   __syncthreads();
-  const int ldo = nx + 2;
+  constexpr bool packed = S == 1;
+  const int ldo = packed ? nx : nx + 2;
 #pragma unroll
-  for (int i = 0; i <= R / 2; ++i) {
+  for (int i = 0; i < R / 2; ++i) {   // k = j + i TPS < Mx; slot k-1 for k >= 1
     const int k = j + i * TPS;
-    if (k == 0 || k >= Mx) continue;
-    ostage[ra * ldo + k - 1] = -(double)v[i].y * scl;
-    ostage[rb * ldo + k - 1] = (double)v[i].x * scl;
+    if (i > 0 || k > 0) {
+      ostage[ra * ldo + k - 1] = -(double)v[i].y * scl;
+      ostage[rb * ldo + k - 1] = (double)v[i].x * scl;
+    }
   }
   __syncthreads();
   double* o = out + (size_t)row0 * nx;
   const int total = nrows * nx;   // < WG * R
   double acc = 0.0;
-  {
+  if (packed && !q) {
+    // one contiguous run: 16-byte moves of pairs, and the odd last value
+    const int npair = total / 2;
+    for (int e = threadIdx.x; e < npair; e += WG)
+      *reinterpret_cast<dpair*>(o + 2 * e) = *reinterpret_cast<const dpair*>(ostage + 2 * e);
+    if ((total & 1) && threadIdx.x == 0) o[total - 1] = ostage[total - 1];
+  } else {
     const double* qq = q ? q + (size_t)row0 * nx : nullptr;
     int r = (int)threadIdx.x / nx, c = (int)threadIdx.x - r * nx;
     const int dr = WG / nx, dc = WG - dr * nx;

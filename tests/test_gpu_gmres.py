@@ -65,7 +65,10 @@ def test_apply_Cinv(nx, ny, nt, alpha):
     z32 = _host(_plan(nx, ny, nt, alpha=alpha, prec="fp32").apply_Cinv(_dev(r[None])))[0]
     # FP32 transforms: rounding amplified by up to 1/alpha by the D_alpha^{-1} scaling
     # (the bound of the FP32 P^{-1} test)
-    assert _rel(z32, ref) < 50 * 6e-8 / alpha
+    err = _rel(z32, ref)
+    print(f"[obs] fp32 C_alpha^-1 alpha={alpha} rel.err {err:.3e}", flush=True)
+    # measured 2.5e-7 (alpha 0.1, 0.5), 8.4e-7 (1e-2), 4.7e-6 .. 6.7e-6 (1e-3), 1.8e-3 (1e-6)
+    assert err < 3e-6 + 2e-8 / alpha
     zn = _host(_plan(nx, ny, nt, alpha=alpha, prec="none").apply_Cinv(_dev(r[None])))[0]
     assert np.array_equal(zn, r)
 
