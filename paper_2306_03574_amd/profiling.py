@@ -3,6 +3,8 @@
     python -m paper_2306_03574_amd.profiling trace <trace_dir> <out.md> --command "..."
     python -m paper_2306_03574_amd.profiling sq <run_dir> [<run_dir> ...] --out <out.md> --kernels REGEX
             --command "..." [--command ...] [--note "..."]
+    python -m paper_2306_03574_amd.profiling bench --entry "LABEL|COMMAND|line.json" ... --out <out.md>
+    python -m paper_2306_03574_amd.profiling serving <lane.json ...> [--without <json>] --out <out.md> --command "..."
     python -m paper_2306_03574_amd.profiling requests <lib_run_dir> --probe NAME=RUN_DIR=USEFUL_BYTES ... --out <out.md>
             --command "..." [--command ...]
     python -m paper_2306_03574_amd.profiling pmc <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir>
@@ -318,6 +320,85 @@ def summarize_requests(lib_dir, probes, out_md, commands, note=""):
     return lines
 
 
+def summarize_bench(entries, out_md, note=""):
+    """One markdown file from bench.py JSON lines: a table row per workload and the full
+    line below it.  `entries`: list of (label, command, json_path)."""
+    rows, blocks = [], []
+    for label, cmd, path in entries:
+        with open(path) as fh:
+            d = json.loads(fh.read().strip().splitlines()[-1])
+        other = next(((k, v) for k, v in d.items() if k.endswith("_precond")), None)
+        oth = f"{other[0].split('_')[0]}: {other[1]['value']} ({other[1]['iters'][0]} it.)" if other else "-"
+        rf = d.get("roofline", {})
+        traffic = rf.get("traffic")
+        tr = f"{traffic / rf['algorithmic_bytes_per_launch']:.3f}" if traffic and rf.get("algorithmic_bytes_per_launch") \
+            else "—"
+        cb = d.get("cpu_baseline") or {}
+        ops = cb.get("per_operator_median_of_3") or cb.get("per_operator") or {}
+        opstr = (f"{ops.get('apply_A_s', '-')} s / {ops.get('apply_Pinv_s', '-')} s" if ops else "-")
+        rows.append(f"| `{label}` | `{cmd}` | {d['value']} {d['unit']} ({d['dtype']}) | {d['ms_per_step']} | "
+                    f"{d['iters'][0]} | {oth} | {rf.get('kernel', '-')}, {rf.get('frac', '-')}, {tr} | "
+                    f"{cb.get('value', '-')} {cb.get('unit', '')} | {opstr} |")
+        blocks += ["", f"`{label}`:", "", "```json", json.dumps(d), "```"]
+    lines = ["# Benchmark lines of every workload (one MI355X, `bench.py`)", "",
+             f"Kernel sources: `{source_sha()}`. Each command runs from the repository root; the full JSON line "
+             "it printed is below its summary. For batched workloads `value` counts right-hand sides per second "
+             "and the oracle solves the first right-hand side. `traffic` is the counter-measured HBM bytes per "
+             "launch of the roofline kernel over its algorithmic bytes (`pmc_<workload>_<prec>.md`; — where no "
+             "record of these sources exists)."]
+    if note:
+        lines += ["", note]
+    lines += ["", "| workload | command | value | ms per step | iterations | other precision | "
+              "roofline kernel, frac, traffic / algorithmic bytes | oracle (cpu_baseline) | oracle apply_A / apply_Pinv |",
+              "|---|---|---:|---:|---:|---:|---|---:|---|"] + rows + blocks
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return rows
+
+
+def summarize_serving(entries, out_md, command, note="", without=()):
+    """The serving sweep from bench.py --workload serving_mix JSON lines: `entries` are
+    the lane runs (one per rate), `without` the same rates with the lane off."""
+    runs = []
+    for path in entries:
+        with open(path) as fh:
+            runs.append(json.loads(fh.read().strip().splitlines()[-1]))
+    lines = ["# Serving sweep (one MI355X, `bench.py --workload serving_mix`)", "",
+             f"Command per rate R, from the repository root: `{command}`."]
+    if note:
+        lines += ["", note]
+    lines += ["", "| offered req/s | completed solves/s | p50 ms | p99 ms | converged | mean iterations |",
+              "|---:|---:|---:|---:|---:|---:|"]
+    for d in runs:
+        c = d["config"]
+        lines.append(f"| {c['rate_per_s']:g} | {d['value']} | {d['p50_ms']} | {d['p99_ms']} | "
+                     f"{d['converged']}/{c['requests']} | {d['mean_iters']} |")
+    if without:
+        parts = []
+        for path in without:
+            with open(path) as fh:
+                d = json.loads(fh.read().strip().splitlines()[-1])
+            parts.append(f"{d['config']['rate_per_s']:g} req/s: {d['value']} solves/s, p50 {d['p50_ms']} ms, "
+                         f"p99 {d['p99_ms']} ms")
+        lines += ["", "Without the lane (`--group-lane 0`, every request on its own stream), same sources: "
+                  + ", ".join(parts) + "."]
+    classes = sorted({k for d in runs for k in d["per_class_p50_p99_ms"]})
+    lines += ["", "Per shape class, p50 / p99 latency in ms (requests of the class in parentheses, at the "
+              "highest rate):", "",
+              "| class | " + " | ".join(f"{d['config']['rate_per_s']:g}/s" for d in runs) + " |",
+              "|---|" + "---:|" * len(runs)]
+    for k in classes:
+        n = runs[-1]["per_class_p50_p99_ms"].get(k, [0, 0, 0])[2]
+        cells = []
+        for d in runs:
+            v = d["per_class_p50_p99_ms"].get(k)
+            cells.append(f"{v[0]} / {v[1]}" if v else "-")
+        lines.append(f"| `{k}` ({n}) | " + " | ".join(cells) + " |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return lines
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -338,6 +419,16 @@ def main():
     rq.add_argument("--out", required=True)
     rq.add_argument("--command", action="append", required=True)
     rq.add_argument("--note", default="")
+    bs = sub.add_parser("bench")
+    bs.add_argument("--entry", action="append", required=True, help="label|command|json_path")
+    bs.add_argument("--out", required=True)
+    bs.add_argument("--note", default="")
+    sv = sub.add_parser("serving")
+    sv.add_argument("jsons", nargs="+")
+    sv.add_argument("--without", action="append", default=[])
+    sv.add_argument("--out", required=True)
+    sv.add_argument("--command", required=True)
+    sv.add_argument("--note", default="")
     p = sub.add_parser("pmc")
     for a in ("fetch_dir", "write_dir", "copy_fetch_dir", "copy_write_dir"):
         p.add_argument(a)
@@ -350,6 +441,14 @@ def main():
     if a.cmd == "sq":
         for name in summarize_sq(a.run_dirs, a.out, a.kernels, a.command, a.note):
             print(name)
+        return
+    if a.cmd == "bench":
+        for r in summarize_bench([tuple(e.split("|")) for e in a.entry], a.out, a.note):
+            print(r)
+        return
+    if a.cmd == "serving":
+        for r in summarize_serving(a.jsons, a.out, a.command, a.note, a.without):
+            print(r)
         return
     if a.cmd == "requests":
         probes = OrderedDict()
