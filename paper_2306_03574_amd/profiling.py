@@ -334,7 +334,7 @@ def summarize_bench(entries, out_md, note=""):
         tr = f"{traffic / rf['algorithmic_bytes_per_launch']:.3f}" if traffic and rf.get("algorithmic_bytes_per_launch") \
             else "—"
         cb = d.get("cpu_baseline") or {}
-        ops = cb.get("per_operator_median_of_3") or cb.get("per_operator") or {}
+        ops = cb.get("per_operator_s") or cb.get("per_operator_median_of_3") or cb.get("per_operator") or {}
         opstr = (f"{ops.get('apply_A_s', '-')} s / {ops.get('apply_Pinv_s', '-')} s" if ops else "-")
         rows.append(f"| `{label}` | `{cmd}` | {d['value']} {d['unit']} ({d['dtype']}) | {d['ms_per_step']} | "
                     f"{d['iters'][0]} | {oth} | {rf.get('kernel', '-')}, {rf.get('frac', '-')}, {tr} | "
