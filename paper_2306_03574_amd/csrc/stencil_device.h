@@ -1,6 +1,7 @@
 // Device code of the Y T matvec (eqs. (1.2), (1.4)): the weights of L at a grid
-// point (constant or variable coefficient) and the band-marching stencil tile.  Shared
-// by the matvec kernels and the fused small-problem iteration.
+// point (constant or variable coefficient) and the band-marching stencil tiles (two
+// columns per thread for the constant coefficient, one for the variable one).  Shared
+// by the matvec kernels, the fused small-problem iteration and the group kernels.
 #pragma once
 #include "abac_internal.h"
 
@@ -70,13 +71,14 @@ __device__ __forceinline__ double apply_L(const LCoef& q, const double* __restri
 // the residual vector f - T x, or only the squared residual norm
 enum StencilOut : int { OUT_REV = 0, OUT_NAT = 1, OUT_RESVEC = 2, OUT_RESNORM = 3 };
 
-// One logical block of the matvec: a band of RB grid rows times st_threads consecutive
-// columns, forward levels [k0, k1) and their mirrors nt-1-k.  Each thread marches one
-// column of the band.  Per level it loads the RB+2 rows of its column (the band and the
-// two rows around it, clamped into the grid: a missing neighbour reads the centre with
-// weight 0, as in l_coef), so the y-neighbours of every row come from registers, and the
-// two x-neighbours of each row (L1 hits).  L of the two previous levels stays in
-// registers.  Every load is unconditional, so a step's loads are all in flight together.
+// One column of a logical block of the matvec, one column per thread (the
+// variable-coefficient tile, and grids one column wide): a band of RB grid rows, forward
+// levels [k0, k1) and their mirrors nt-1-k.  Per level it loads the RB+2 rows of its
+// column (the band and the two rows around it, clamped into the grid: a missing
+// neighbour reads the centre with weight 0, as in l_coef), so the y-neighbours of every
+// row come from registers, and the two x-neighbours of each row (L1 hits).  L of the two
+// previous levels stays in registers.  Every load is unconditional, so a step's loads
+// are all in flight together.
 // VAR: variable coefficient, face weights per row; otherwise the x weights depend on the
 // column only and the y weights on the (block-uniform) row only.
 template <int RB, bool VAR>
