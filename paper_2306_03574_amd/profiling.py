@@ -41,14 +41,23 @@ CLASS_OF = OrderedDict([
 ])
 
 
-def source_sha() -> str:
-    """Hash of the HIP sources of the library (names and contents)."""
+def code_text(text: str) -> str:
+    """C++ source without its comments, whitespace runs collapsed: what a change to the
+    kernels has to touch (the sources hold no string literal with comment markers)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def source_sha(csrc: str = None) -> str:
+    """Hash of the HIP sources of the library (file names and code; comments and layout
+    do not count, so a counter record stays valid across comment edits)."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2306_03574_amd", "csrc")
+    csrc = csrc or os.path.join(ROOT, "paper_2306_03574_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as fh:
+        with open(os.path.join(csrc, name), encoding="utf-8") as fh:
             h.update(name.encode())
-            h.update(fh.read())
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
