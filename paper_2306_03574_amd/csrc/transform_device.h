@@ -242,23 +242,26 @@ __device__ __forceinline__ void dsty_tile(const DevPlan& P, int b, int lbk) {
   C* col = reinterpret_cast<C*>(reinterpret_cast<T*>(P.scratch) + (size_t)b * P.NS + (size_t)t * P.ms) +
            min(cp, cpairs - 1);   // clamped: the loads below are unconditional
   C v[R];
-  // odd extension of the column: element tt is x[tt-1] for 0 < tt < My, -x[2 My - tt - 1]
-  // for tt > My, 0 at tt = 0 and tt = My
+  // each column value is loaded once (elements tt = j + i TPS < My, i < R/2) and placed
+  // in LDS at tt and, negated, at its mirror 2 My - tt: the odd extension in natural
+  // order, from which the FFT reads its input
 #pragma unroll
-  for (int i = 0; i < R; ++i) {
+  for (int i = 0; i < R / 2; ++i) {
     const int tt = j + i * TPS;
-    const int src = tt < My ? max(tt - 1, 0) : min(2 * My - tt - 1, My - 2);
-    v[i] = col[(size_t)src * ld];
+    v[i] = col[(size_t)max(tt - 1, 0) * ld];
   }
+  C* my = lds + s;
 #pragma unroll
-  for (int i = 0; i < R; ++i) {
+  for (int i = 0; i < R / 2; ++i) {
     const int tt = j + i * TPS;
-    const bool zero = !valid || tt == 0 || tt == My;
-    v[i] = zero ? C{0, 0} : (tt < My ? v[i] : C{-v[i].x, -v[i].y});
+    const C x = !valid || tt == 0 ? C{0, 0} : v[i];
+    my[tt * S] = x;
+    if (tt > 0) my[(2 * My - tt) * S] = C{-x.x, -x.y};
   }
+  if (j == 0) my[My * S] = C{0, 0};
   stage_table(tws, reinterpret_cast<const C*>(P.twy), L);
   __syncthreads();
-  fft_seq<T, L, false>(v, j, lds + s, S, tws);
+  fft_seq<T, L, false, true>(v, j, my, S, tws);
   const T scl = (T)(1.0 / sqrt((double)L));
   if (!valid) return;
 #pragma unroll
