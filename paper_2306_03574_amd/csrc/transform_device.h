@@ -551,13 +551,12 @@ __device__ __forceinline__ double dstx_inv_tile(const DevPlan& P, int mode, doub
   __syncthreads();
   fft_seq<T, L, false>(v, j, lds + s, S, tw);
   const double scl = 1.0 / sqrt((double)L);
-  // stage the FP64 rows and write them out contiguously; with q, accumulate <q, p> in a
-  // fixed order for a fixed tile.  Rows are [2S][nx+2] (odd stride in 8-byte words, so
-  // the sequences of a wave write different banks), or packed [2][nx] with one sequence
-  // per block, where the block's output is then one contiguous run.
+  // stage the FP64 rows packed ([2S][nx]: the block's 2S output rows are one contiguous
+  // run of memory, and the odd row length in 8-byte words spreads the sequences of a
+  // wave over the banks) and write them out; with q, accumulate <q, p> in a fixed order
+  // for a fixed tile
   __syncthreads();
-  constexpr bool packed = S == 1;
-  const int ldo = packed ? nx : nx + 2;
+  const int ldo = nx;
 #pragma unroll
   for (int i = 0; i < R / 2; ++i) {   // k = j + i TPS < Mx; slot k-1 for k >= 1
     const int k = j + i * TPS;
@@ -570,7 +569,7 @@ __device__ __forceinline__ double dstx_inv_tile(const DevPlan& P, int mode, doub
   double* o = out + (size_t)row0 * nx;
   const int total = nrows * nx;   // < WG * R
   double acc = 0.0;
-  if (packed && !q) {
+  if (!q) {
     // one contiguous run: 16-byte moves of pairs, and the odd last value
     const int npair = total / 2;
     for (int e = threadIdx.x; e < npair; e += WG)
