@@ -400,6 +400,54 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def run_group_compare(args):
+    """Time per MINRES iteration of mixed-grid groups (abac_group_*): one launch per step
+    (advance) against one persistent launch (run) at several grid sizes.  Sources are
+    random, the tolerance unreachable, so every iteration does the full work."""
+    import torch
+    from paper_2306_03574_amd import Plan, Group
+    import synth
+    DEV = torch.device("cuda:0")
+    prec = args.prec or "fp32"
+    grids = [int(x) for x in args.group_blocks.split(",")]
+    K = args.steps
+    out = {"metric": "group iteration time", "unit": "us per iteration", "prec": prec, "iterations": K,
+           "higher_is_better": False, "data": "synthetic", "mixes": {}}
+    for name in args.group_compare.split(","):
+        cases = synth.workloads.GROUP_MIXES[name]
+        log(f"group mix {name} ({len(cases)} members) {prec}")
+        plans, fs, us = [], [], []
+        for i, (nx, ny, nt, a) in enumerate(cases):
+            p = Plan(nx, ny, nt, alpha=a, prec=prec, batch=1, device=DEV)
+            src, z0, z1 = synth.random_source(nx, ny, nt, seed=50 + i)
+            fs.append(p.build_rhs(torch.from_numpy(src[None]).to(DEV), torch.from_numpy(z0[None]).to(DEV),
+                                  torch.from_numpy(z1[None]).to(DEV)))
+            us.append(p.empty())
+            plans.append(p)
+        res = {}
+        for mode in ["advance"] + [f"run{b}" for b in grids]:
+            for p, f, u in zip(plans, fs, us):
+                p.begin(f, u, tol=1e-30, maxit=1 << 20)
+            g = Group(device=DEV)
+            g.set(plans)
+            blocks = None if mode == "advance" else int(mode[3:])
+            step = (lambda k: g.advance(k)) if blocks is None else (lambda k: g.run(k, blocks=blocks))
+            step(args.warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            step(K)
+            torch.cuda.synchronize()
+            res[mode] = round((time.perf_counter() - t0) / K * 1e6, 1)
+            if blocks is not None and g.check():
+                raise RuntimeError(f"persistent launch of mix {name} gave up at a barrier")
+            for p in plans:
+                p.finish()
+            g.close()
+            log(f"  {mode}: {res[mode]} us per iteration")
+        out["mixes"][name] = {"members": [list(c) for c in cases], "us_per_iteration": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -427,9 +475,17 @@ def main():
                     help="minres: Y T u = Y f with the ABAC preconditioner (the method); gmres: T u = f "
                          "right-preconditioned by the block alpha-circulant C_alpha")
     ap.add_argument("--restart", type=int, default=15, help="gmres: restart length (<= 15)")
+    ap.add_argument("--group-compare", default=None,
+                    help="only time groups of these mixes (comma-separated, synth.workloads.GROUP_MIXES): one "
+                         "launch per step against one persistent launch; --steps iterations timed")
+    ap.add_argument("--group-blocks", default="0,64,128,256",
+                    help="group compare: persistent grid sizes (0 = the library's default)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(int(args.copy_gib * (1 << 30)) // 128 * 128 if args.copy_gib else None, args.copy_pattern)
+        return
+    if args.group_compare:
+        run_group_compare(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single GPU and sharding one solve over "

@@ -28,7 +28,8 @@ EXPORTED = [
     "abac_server_submit", "abac_server_step", "abac_server_result", "abac_server_clock",
     "abac_server_bytes_in_use", "abac_plan_tiles", "abac_plan_set_coefficient", "abac_apply_T", "abac_apply_Cinv",
     "abac_gmres_solve", "abac_plan_set_tiles", "abac_apply_Pinv_noalloc", "abac_group_create",
-    "abac_group_destroy", "abac_group_set", "abac_group_advance", "abac_server_group_lane",
+    "abac_group_destroy", "abac_group_set", "abac_group_advance", "abac_group_run", "abac_group_check",
+    "abac_server_group_lane",
 ]
 
 _lib = None
@@ -119,6 +120,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abac_group_set.restype = I
     lib.abac_group_advance.argtypes = [P, I]
     lib.abac_group_advance.restype = I
+    lib.abac_group_run.argtypes = [P, I, I, D]
+    lib.abac_group_run.restype = I
+    lib.abac_group_check.argtypes = [P, ctypes.POINTER(I)]
+    lib.abac_group_check.restype = I
     lib.abac_plan_set_tiles.argtypes = [P, I, I, I, I]
     lib.abac_plan_set_tiles.restype = I
     lib.abac_server_bytes_in_use.argtypes = [P]
@@ -383,6 +388,18 @@ class Group:
 
     def advance(self, iterations: int = 1):
         _check(self._lib.abac_group_advance(self._h, int(iterations)), "abac_group_advance")
+
+    def run(self, iterations: int = 1, blocks: int = 0, timeout_s: float = 0.0):
+        """The same iterations as advance(), in one persistent launch of `blocks`
+        workgroups (0: the library's default) (abac_group_run)."""
+        _check(self._lib.abac_group_run(self._h, int(iterations), int(blocks), float(timeout_s)),
+               "abac_group_run")
+
+    def check(self) -> bool:
+        """Whether a persistent launch gave up at a barrier since the last check."""
+        flag = ctypes.c_int(0)
+        _check(self._lib.abac_group_check(self._h, ctypes.byref(flag)), "abac_group_check")
+        return bool(flag.value)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

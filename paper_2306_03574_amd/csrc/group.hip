@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -32,6 +34,7 @@ namespace {
 constexpr int kGroupWG = 256;
 constexpr int kGroupFinThreads = 1024;   // as the members' scalar-step kernel
 constexpr int kGroupMax = 64;
+constexpr double kGroupTimeout = 2.0;    // seconds a persistent block waits at a barrier
 
 enum GroupStep : int { GS_STENCIL = 0, GS_XFWD, GS_Y, GS_TIME, GS_XINV, GS_VEC, GS_FIN, GS_COUNT };
 
@@ -76,8 +79,8 @@ __device__ __forceinline__ Where locate(const GroupTable* __restrict__ G, int st
 // ---- matvec: one logical block per workgroup, lanes beyond the member's column tile
 // idle (they add 0 to the block's sum, so the partial is the member kernel's) ---------
 template <int MODE>
-__global__ void __launch_bounds__(kGroupWG) k_group_stencil(const GroupTable* __restrict__ G) {
-  const Where at = locate(G, GS_STENCIL, blockIdx.x);
+__device__ __forceinline__ void group_stencil(const GroupTable* __restrict__ G, int w) {
+  const Where at = locate(G, GS_STENCIL, w);
   const GroupMember& M = G->m[at.r];
   const DevPlan& P = M.P;
   const MinresState* st = P.st + at.b;
@@ -105,8 +108,36 @@ __global__ void __launch_bounds__(kGroupWG) k_group_stencil(const GroupTable* __
 }
 
 // ---- scalar steps: one workgroup per right-hand side --------------------------------
-__global__ void __launch_bounds__(kGroupFinThreads) k_group_fin(const GroupTable* __restrict__ G, int kind) {
-  const Where at = locate(G, GS_FIN, blockIdx.x);
+// The fixed-order sum of n partials exactly as a block of V threads forms it (that of
+// sum_parts with blockDim.x = V), computed by a block of blockDim.x threads, where
+// blockDim.x divides V <= 1024: thread t stands in for threads t, t + blockDim.x, ...
+// of the V-thread block, whose 64-lane waves it reduces one after the other, so every
+// addition and its order are the V-thread block's.  Result valid in thread 0.
+__device__ __forceinline__ double sum_parts_as(const double* __restrict__ part, int n, int V) {
+  __shared__ double wsum[16];
+  const double2* p2 = reinterpret_cast<const double2*>(part);
+  const int n2 = n >> 1, lane = threadIdx.x & 63;
+  for (int vt = threadIdx.x; vt < V; vt += blockDim.x) {
+    double s = 0.0;
+    for (int i = vt; i < n2; i += V) {
+      const double2 v = p2[i];
+      s += v.x + v.y;
+    }
+    if ((n & 1) && vt == 0) s += part[n - 1];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) wsum[vt >> 6] = s;
+  }
+  __syncthreads();
+  double tot = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (V + 63) >> 6; ++i) tot += wsum[i];
+  __syncthreads();
+  return tot;
+}
+
+__device__ __forceinline__ void group_fin(const GroupTable* __restrict__ G, int w, int kind) {
+  const Where at = locate(G, GS_FIN, w);
   const DevPlan& P = G->m[at.r].P;
   if (!fin_begin(P, at.b, kind)) return;
   int nparts;
@@ -118,13 +149,13 @@ __global__ void __launch_bounds__(kGroupFinThreads) k_group_fin(const GroupTable
     case FIN_GAMMA_ITER: nparts = P.gamma_nparts; break;
     default: nparts = stencil_blocks(P); break;
   }
-  const double tot = sum_parts(part_slot(P, fin_part_kind(kind), at.b), nparts);
+  const double tot = sum_parts_as(part_slot(P, fin_part_kind(kind), at.b), nparts, kGroupFinThreads);
   if (threadIdx.x == 0) fin_scalar(P, at.b, kind, tot, 0.0, 0);
 }
 
 // ---- vector steps: residual recurrence, iterate from the basis ----------------------
-__global__ void __launch_bounds__(kGroupWG) k_group_update(const GroupTable* __restrict__ G) {
-  const Where at = locate(G, GS_VEC, blockIdx.x);
+__device__ __forceinline__ void group_update(const GroupTable* __restrict__ G, int w) {
+  const Where at = locate(G, GS_VEC, w);
   const GroupMember& M = G->m[at.r];
   const DevPlan& P = M.P;
   if (P.st[at.b].state != ST_RUNNING) return;
@@ -133,8 +164,8 @@ __global__ void __launch_bounds__(kGroupWG) k_group_update(const GroupTable* __r
   if (threadIdx.x == 0) part_slot(P, PART_RNORM, at.b)[at.lbk] = bs;
 }
 
-__global__ void __launch_bounds__(kGroupWG) k_group_form(const GroupTable* __restrict__ G) {
-  const Where at = locate(G, GS_VEC, blockIdx.x);
+__device__ __forceinline__ void group_form(const GroupTable* __restrict__ G, int w) {
+  const Where at = locate(G, GS_VEC, w);
   const GroupMember& M = G->m[at.r];
   const DevPlan& P = M.P;
   const MinresState* st = P.st + at.b;
@@ -151,8 +182,8 @@ __global__ void __launch_bounds__(kGroupWG) k_group_form(const GroupTable* __res
 
 // first pass: the Lanczos step and the x-DST, or the fused x-y pass
 template <typename T>
-__global__ void __launch_bounds__(kGroupWG) k_group_xfwd(const GroupTable* __restrict__ G) {
-  const Where at = locate(G, GS_XFWD, blockIdx.x);
+__device__ __forceinline__ void group_xfwd(const GroupTable* __restrict__ G, int w) {
+  const Where at = locate(G, GS_XFWD, w);
   const DevPlan& P = G->m[at.r].P;
   if (P.st[at.b].state != ST_RUNNING) return;
   constexpr int mode = FWD_LANCZOS;
@@ -175,8 +206,8 @@ __global__ void __launch_bounds__(kGroupWG) k_group_xfwd(const GroupTable* __res
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kGroupWG) k_group_y(const GroupTable* __restrict__ G) {
-  const Where at = locate(G, GS_Y, blockIdx.x);
+__device__ __forceinline__ void group_y(const GroupTable* __restrict__ G, int w) {
+  const Where at = locate(G, GS_Y, w);
   const DevPlan& P = G->m[at.r].P;
   if (P.st[at.b].state != ST_RUNNING) return;
   const int lbk = xcd_remap(at.lbk, at.per);
@@ -187,8 +218,8 @@ __global__ void __launch_bounds__(kGroupWG) k_group_y(const GroupTable* __restri
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kGroupWG) k_group_time(const GroupTable* __restrict__ G) {
-  const Where at = locate(G, GS_TIME, blockIdx.x);
+__device__ __forceinline__ void group_time(const GroupTable* __restrict__ G, int w) {
+  const Where at = locate(G, GS_TIME, w);
   const DevPlan& P = G->m[at.r].P;
   if (P.st[at.b].state != ST_RUNNING) return;
   const int lbk = xcd_remap(at.lbk, at.per);
@@ -200,9 +231,9 @@ __global__ void __launch_bounds__(kGroupWG) k_group_time(const GroupTable* __res
 
 // last pass: writes z_{j+1}; <q, P^{-1} q> came from the time pass
 template <typename T>
-__global__ void __launch_bounds__(kGroupWG) k_group_xinv(const GroupTable* __restrict__ G) {
+__device__ __forceinline__ void group_xinv(const GroupTable* __restrict__ G, int w) {
   constexpr int mode = INV_Z_ITER;
-  const Where at = locate(G, GS_XINV, blockIdx.x);
+  const Where at = locate(G, GS_XINV, w);
   const DevPlan& P = G->m[at.r].P;
   if (P.st[at.b].state != ST_RUNNING) return;
   const int L = 2 * P.Mx;
@@ -226,6 +257,139 @@ __global__ void __launch_bounds__(kGroupWG) k_group_xinv(const GroupTable* __res
 #undef ABAC_GROUP_SLAB_LENGTHS
 #undef ABAC_GROUP_T_LENGTHS
 
+// ---- list kernels: one launch per step, one logical block per workgroup -------------
+template <int MODE>
+__global__ void __launch_bounds__(kGroupWG) k_group_stencil(const GroupTable* __restrict__ G) {
+  group_stencil<MODE>(G, blockIdx.x);
+}
+__global__ void __launch_bounds__(kGroupFinThreads) k_group_fin(const GroupTable* __restrict__ G, int kind) {
+  group_fin(G, blockIdx.x, kind);
+}
+__global__ void __launch_bounds__(kGroupWG) k_group_update(const GroupTable* __restrict__ G) {
+  group_update(G, blockIdx.x);
+}
+__global__ void __launch_bounds__(kGroupWG) k_group_form(const GroupTable* __restrict__ G) {
+  group_form(G, blockIdx.x);
+}
+template <typename T>
+__global__ void __launch_bounds__(kGroupWG) k_group_xfwd(const GroupTable* __restrict__ G) {
+  group_xfwd<T>(G, blockIdx.x);
+}
+template <typename T>
+__global__ void __launch_bounds__(kGroupWG) k_group_y(const GroupTable* __restrict__ G) {
+  group_y<T>(G, blockIdx.x);
+}
+template <typename T>
+__global__ void __launch_bounds__(kGroupWG) k_group_time(const GroupTable* __restrict__ G) {
+  group_time<T>(G, blockIdx.x);
+}
+template <typename T>
+__global__ void __launch_bounds__(kGroupWG) k_group_xinv(const GroupTable* __restrict__ G) {
+  group_xinv<T>(G, blockIdx.x);
+}
+
+// ---- persistent kernel: every step of `iterations` iterations in one launch ---------
+// Barrier state in device memory.  count and gen are reset before each launch; aborted
+// stays set until the host reads it (abac_group_check).
+struct GridSync {
+  unsigned count;   // blocks arrived at the current barrier
+  unsigned gen;     // barriers completed in this launch
+  int abort;        // a block stopped waiting: every block leaves the launch
+  int aborted;      // sticky copy of abort
+};
+
+// Grid-wide barrier.  Inside one launch the L2s of the XCDs are not coherent with each
+// other.  Every wave waits until its stores have reached its XCD's L2, then, after the
+// workgroup barrier, thread 0 counts the block in with an agent-scope acquire-release
+// atomic (which writes that L2 back first), the last block to arrive opens the next
+// generation, and every wave acquires at agent scope after it.  A waiting
+// block gives up once `deadline` ticks of the constant-rate clock have passed or
+// another block gave up; false then tells every thread of the block to leave the
+// kernel, so the launch always ends.
+__device__ __forceinline__ bool grid_barrier(GridSync* gs, unsigned& gen, unsigned long long deadline) {
+  __shared__ int pass;
+  __builtin_amdgcn_s_waitcnt(0);   // this wave's stores have reached its XCD's L2
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned next = gen + 1;
+    int ok = 1;
+    if (__hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1) {
+      __hip_atomic_store(&gs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&gs->gen, next, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const unsigned long long t0 = wall_clock64();
+      while (__hip_atomic_load(&gs->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != next) {
+        if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+            wall_clock64() - t0 > deadline) {
+          __hip_atomic_store(&gs->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&gs->aborted, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    gen = next;
+    pass = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return pass;
+}
+
+// The step bodies, out of line so that each gets the registers of its own tile (inlined
+// into one loop they would all share the largest tile's and spill).
+template <int MODE>
+__device__ __noinline__ void ps_stencil(const GroupTable* G, int w) { group_stencil<MODE>(G, w); }
+__device__ __noinline__ void ps_fin(const GroupTable* G, int w, int kind) { group_fin(G, w, kind); }
+__device__ __noinline__ void ps_update(const GroupTable* G, int w) { group_update(G, w); }
+__device__ __noinline__ void ps_form(const GroupTable* G, int w) { group_form(G, w); }
+template <typename T>
+__device__ __noinline__ void ps_xfwd(const GroupTable* G, int w) { group_xfwd<T>(G, w); }
+template <typename T>
+__device__ __noinline__ void ps_y(const GroupTable* G, int w) { group_y<T>(G, w); }
+template <typename T>
+__device__ __noinline__ void ps_time(const GroupTable* G, int w) { group_time<T>(G, w); }
+template <typename T>
+__device__ __noinline__ void ps_xinv(const GroupTable* G, int w) { group_xinv<T>(G, w); }
+
+// The grid is at most what the device holds at once (a cooperative launch); block k
+// takes logical blocks k, k + gridDim.x, ... of each step, then the grid meets at a
+// barrier, so a step starts only once the step before has finished for every member,
+// as between the list kernels.  Each logical block runs the same body with the same
+// workgroup size as in the list kernels (the scalar steps' sums keep the order of
+// their 1024-thread blocks), so the results are bitwise those of abac_group_advance.
+template <typename T>
+__global__ void __launch_bounds__(kGroupWG)
+k_group_persistent(const GroupTable* __restrict__ G, int iterations, GridSync* gs, unsigned long long deadline) {
+  unsigned gen = 0;
+  const int n = G->n;
+  for (int it = 0; it < iterations; ++it) {
+#define ABAC_STEP(STEP, CALL)                                             \
+    if (G->off[STEP][n]) {                                                \
+      for (int w = blockIdx.x; w < G->off[STEP][n]; w += gridDim.x) {     \
+        CALL;                                                             \
+        __syncthreads();                                                  \
+      }                                                                   \
+      if (!grid_barrier(gs, gen, deadline)) return;                       \
+    }
+    ABAC_STEP(GS_STENCIL, ps_stencil<STENCIL_MINRES>(G, w))
+    ABAC_STEP(GS_FIN, ps_fin(G, w, FIN_DELTA))
+    ABAC_STEP(GS_XFWD, ps_xfwd<T>(G, w))
+    ABAC_STEP(GS_Y, ps_y<T>(G, w))
+    ABAC_STEP(GS_TIME, ps_time<T>(G, w))
+    ABAC_STEP(GS_Y, ps_y<T>(G, w))
+    ABAC_STEP(GS_XINV, ps_xinv<T>(G, w))
+    ABAC_STEP(GS_FIN, ps_fin(G, w, FIN_GAMMA_ITER))
+    ABAC_STEP(GS_VEC, ps_update(G, w))
+    ABAC_STEP(GS_FIN, ps_fin(G, w, FIN_RNORM))
+    ABAC_STEP(GS_VEC, ps_form(G, w))
+    ABAC_STEP(GS_STENCIL, ps_stencil<STENCIL_RESIDUAL>(G, w))
+    ABAC_STEP(GS_FIN, ps_fin(G, w, FIN_RES))
+#undef ABAC_STEP
+  }
+}
+
 }  // namespace
 }  // namespace abac
 
@@ -245,6 +409,7 @@ struct abac_group {
   size_t lds[GS_COUNT];
   hipEvent_t joined;             // members' set-up done (recorded on each member stream in turn)
   hipEvent_t done;               // the group's last enqueued work
+  GridSync* d_sync;              // barrier state of the persistent kernel
 };
 
 namespace {
@@ -329,6 +494,24 @@ abac_status group_iteration(abac_group* g) {
   return ABAC_OK;
 }
 
+// each member's snapshot of every enqueued iteration is complete behind this point
+abac_status post_snapshots(abac_group* g, int iterations) {
+  for (int it = 0; it < iterations; ++it)
+    for (abac_plan* p : g->members) {
+      const int slot = (int)(p->ring_posted % kSnapRing);
+      GHIP(hipEventRecord(p->ring_ev[slot], g->stream));
+      p->ring_posted++;
+    }
+  return ABAC_OK;
+}
+
+abac_status check_members(abac_group* g, int iterations) {
+  if (iterations < 0) return gfail(ABAC_EINVAL, "iterations must be >= 0");
+  for (abac_plan* p : g->members)
+    if (!p->active) return gfail(ABAC_EINVAL, "a member's solve was finished; set the group again");
+  return ABAC_OK;
+}
+
 // every member's stream waits for the group's work so far (later calls on a member,
 // such as abac_minres_finish, are ordered after it)
 abac_status group_release(abac_group* g) {
@@ -363,9 +546,12 @@ abac_status abac_group_create(void* stream, abac_group** out) {
     g->stage_ev[k] = nullptr;
   }
   g->joined = g->done = nullptr;
+  g->d_sync = nullptr;
   std::memset(g->blocks, 0, sizeof(g->blocks));
   std::memset(g->lds, 0, sizeof(g->lds));
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&g->d_table), sizeof(GroupTable));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&g->d_sync), sizeof(GridSync));
+  if (e == hipSuccess) e = hipMemsetAsync(g->d_sync, 0, sizeof(GridSync), g->stream);
   for (int k = 0; e == hipSuccess && k < kGroupStage; ++k) {
     e = hipHostMalloc(reinterpret_cast<void**>(&g->h_stage[k]), sizeof(GroupTable), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&g->stage_ev[k], hipEventDisableTiming);
@@ -390,6 +576,7 @@ abac_status abac_group_destroy(abac_group* g) {
   if (g->joined) (void)hipEventDestroy(g->joined);
   if (g->done) (void)hipEventDestroy(g->done);
   if (g->d_table) (void)hipFree(g->d_table);
+  if (g->d_sync) (void)hipFree(g->d_sync);
   delete g;
   return ABAC_OK;
 }
@@ -450,19 +637,67 @@ abac_status abac_group_set(abac_group* g, abac_plan* const* plans, int n) {
 abac_status abac_group_advance(abac_group* g, int iterations) {
   set_last_error("");
   if (!g) return gfail(ABAC_EINVAL, "NULL group");
-  if (iterations < 0) return gfail(ABAC_EINVAL, "iterations must be >= 0");
-  for (abac_plan* p : g->members)
-    if (!p->active) return gfail(ABAC_EINVAL, "a member's solve was finished; set the group again");
+  GRUN(check_members(g, iterations));
   for (int it = 0; it < iterations && !g->members.empty(); ++it) {
     GRUN(g->prec == ABAC_PREC_FP32 ? group_iteration<float>(g) : group_iteration<double>(g));
-    // each member's snapshot of this iteration is complete behind this point
-    for (abac_plan* p : g->members) {
-      const int slot = (int)(p->ring_posted % kSnapRing);
-      GHIP(hipEventRecord(p->ring_ev[slot], g->stream));
-      p->ring_posted++;
-    }
+    GRUN(post_snapshots(g, 1));
   }
   return group_release(g);
+}
+
+abac_status abac_group_run(abac_group* g, int iterations, int blocks, double timeout_s) {
+  set_last_error("");
+  if (!g) return gfail(ABAC_EINVAL, "NULL group");
+  GRUN(check_members(g, iterations));
+  if (!(timeout_s >= 0) || timeout_s > 3600) return gfail(ABAC_EINVAL, "timeout_s must be in [0, 3600]");
+  if (blocks < 0) return gfail(ABAC_EINVAL, "blocks must be >= 0");
+  if (iterations == 0 || g->members.empty()) return group_release(g);
+  const void* fn = g->prec == ABAC_PREC_FP32 ? reinterpret_cast<const void*>(&k_group_persistent<float>)
+                                             : reinterpret_cast<const void*>(&k_group_persistent<double>);
+  size_t lds = 0;
+  int most = 0;
+  for (int k = 0; k < GS_COUNT; ++k) {
+    if (k != GS_FIN) lds = std::max(lds, g->lds[k]);
+    most = std::max(most, g->blocks[k]);
+  }
+  int dev = 0, ncu = 0, per_cu = 0, coop = 0, khz = 0;
+  GHIP(hipGetDevice(&dev));
+  GHIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  if (!coop) return gfail(ABAC_EDEVICE, "the device does not support cooperative launches");
+  GHIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  GHIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  GHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kGroupWG, lds));
+  if (per_cu < 1) return gfail(ABAC_EINVAL, "the members' tiles leave no room for a persistent block");
+  // Every block must be resident at once.  A barrier costs each block its own L2
+  // write-back and invalidation, which the XCDs serve one block after another (about
+  // 65 ns per block on MI355X), while fewer blocks take more logical blocks each (a few
+  // microseconds per tile).  The default balances the two, sqrt(48 x the largest
+  // step's logical blocks); a multiple of the 8 XCDs keeps the logical blocks of a step
+  // on the XCDs the list kernels would give them.
+  int grid = blocks ? blocks : (int)std::lround(std::sqrt(48.0 * most));
+  grid = std::max(1, std::min(std::min(grid, per_cu * ncu), most));
+  if (grid >= 8) grid -= grid % 8;
+  unsigned long long deadline =
+      (unsigned long long)((timeout_s > 0 ? timeout_s : kGroupTimeout) * (double)khz * 1000.0);
+  // a fresh barrier (count, gen, abort); the sticky flag stays for abac_group_check
+  GHIP(hipMemsetAsync(g->d_sync, 0, offsetof(GridSync, aborted), g->stream));
+  GroupTable* table = g->d_table;
+  GridSync* sync = g->d_sync;
+  void* args[] = {&table, &iterations, &sync, &deadline};
+  GHIP(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kGroupWG), args, (unsigned)lds, g->stream));
+  GRUN(post_snapshots(g, iterations));
+  return group_release(g);
+}
+
+abac_status abac_group_check(abac_group* g, int* aborted) {
+  set_last_error("");
+  if (!g || !aborted) return gfail(ABAC_EINVAL, "NULL argument");
+  int flag = 0;
+  GHIP(hipStreamSynchronize(g->stream));
+  GHIP(hipMemcpy(&flag, &g->d_sync->aborted, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) GHIP(hipMemset(&g->d_sync->aborted, 0, sizeof(int)));
+  *aborted = flag;
+  return ABAC_OK;
 }
 
 }  // extern "C"

@@ -124,6 +124,19 @@ def serving_trace(rate: float, count: int, seed: int = 5):
     return out
 
 
+# Mixes of grids solved as one group, (nx, ny, nt, alpha) per member, sources from
+# random_source with seed 50 + member index: many tiny 1D solves, small 2D and 1D
+# solves, shapes of the serving mix (those with 256-thread tiles), and one C2-sized
+# solve alone.
+GROUP_MIXES = {
+    "1d16": [(255, 0, 64, 1e-3)] * 16,
+    "small8": [(63, 63, 64, 1e-3)] * 4 + [(1023, 0, 64, 1e-3)] * 4,
+    "serving7": [(63, 63, 256, 1e-2), (127, 127, 64, 1e-3), (255, 0, 512, 1e-3), (1023, 0, 256, 1e-2),
+                 (63, 63, 64, 1e-3), (255, 0, 256, 1e-2), (127, 127, 256, 1e-3)],
+    "big1": [(255, 255, 256, 1e-3)],
+}
+
+
 # The five workloads (name -> description used in reports).
 WORKLOADS = {
     "wave1d_63x64": "1D, nx=63, nt=64, T=1, manufactured u=sin(pi x)sin(pi t) + N(0, 0.1^2) source noise (seed 1)",

@@ -1,8 +1,8 @@
 // Exercises the host side of the C ABI (include/abac.h) end to end: plan creation with
 // library- and caller-owned workspaces, the operators, synchronous and asynchronous
-// MINRES, GMRES, a variable coefficient, tile overrides, kernel timing, groups, the
-// request server with its group lane, the allocation-free P^{-1} entry point, and the
-// argument checks of each.  Built with the host code of the library under
+// MINRES, GMRES, a variable coefficient, tile overrides, kernel timing, groups (one launch
+// per step and persistent), the request server with its group lane, the allocation-free
+// P^{-1} entry point, and the argument checks of each.  Built with the host code of the library under
 // AddressSanitizer (device code is not instrumented), it turns any out-of-bounds,
 // use-after-free or double free in the host layer into a report and a non-zero exit.
 // Prints HOST_DRIVER_OK when every call returned what it should.
@@ -151,8 +151,12 @@ static void group_of_three() {
     abac_plan* twice[2] = {p[0], p[0]};
     EXPECT(abac_group_set(g, twice, 2) == ABAC_EINVAL);
     EXPECT(abac_group_set(g, p, 3) == ABAC_OK);
+    EXPECT(abac_group_run(g, 1, -1, 0.0) == ABAC_EINVAL);
+    EXPECT(abac_group_run(g, 1, 0, -1.0) == ABAC_EINVAL);
+    EXPECT(abac_group_check(g, nullptr) == ABAC_EINVAL);
     for (int k = 0; k < 200; ++k) {
-      EXPECT(abac_group_advance(g, 1) == ABAC_OK);
+      // one launch per step, then every step of two iterations in one persistent launch
+      EXPECT((k < 2 ? abac_group_advance(g, 1) : abac_group_run(g, 2, 0, 0.0)) == ABAC_OK);
       int all = 1;
       for (int i = 0; i < 3; ++i) {
         int d = 0;
@@ -161,6 +165,9 @@ static void group_of_three() {
       }
       if (all) break;
     }
+    int aborted = 1;
+    EXPECT(abac_group_check(g, &aborted) == ABAC_OK);
+    EXPECT(aborted == 0);
     EXPECT(abac_group_destroy(g) == ABAC_OK);
   }
   for (int i = 0; i < 3; ++i) {

@@ -57,18 +57,27 @@ def _solo(case, prec, seed):
     return _host(f), _host(u), iters, relres, status
 
 
-def _run_group(g, plans, limit):
-    for _ in range(limit):
-        g.advance(1)
+def _step(g, k, persistent, blocks=0):
+    if persistent:
+        g.run(k, blocks=blocks)
+    else:
+        g.advance(k)
+
+
+def _run_group(g, plans, limit, persistent=False, chunk=1, blocks=0):
+    for _ in range(0, limit, chunk):
+        _step(g, chunk, persistent, blocks)
         torch.cuda.synchronize()
         if all(p.poll() for p in plans):
             return
     raise AssertionError("group did not finish")
 
 
-def _check_members(cases, prec, seeds, late=()):
+def _check_members(cases, prec, seeds, late=(), persistent=False, chunk=1, blocks=0):
     """Solve `cases` as one group (those in `late` join after two iterations of the
-    others) and compare every member with its solo solve."""
+    others) and compare every member with its solo solve.  persistent: every
+    `chunk` iterations run as one persistent launch (abac_group_run) of `blocks`
+    workgroups (0: the library's default)."""
     from paper_2306_03574_amd import Group
     solo = [_solo(c, prec, s) for c, s in zip(cases, seeds)]
     plans, fs, us = [], [], []
@@ -82,15 +91,17 @@ def _check_members(cases, prec, seeds, late=()):
     early = [i for i in range(len(cases)) if i not in late]
     for i in early:
         plans[i].begin(fs[i], us[i], tol=TOL, maxit=MAXIT)
-    _say(f"group of {len(early)} {prec}")
+    _say(f"group of {len(early)} {prec} persistent={persistent} chunk={chunk} blocks={blocks}")
     g.set([plans[i] for i in early])
-    g.advance(2)
+    _step(g, 2, persistent, blocks)
     if late:
         for i in late:
             plans[i].begin(fs[i], us[i], tol=TOL, maxit=MAXIT)
         _say(f"group of {len(cases)} {prec} (late members joined)")
         g.set(plans)
-    _run_group(g, plans, MAXIT + 2)
+    _run_group(g, plans, MAXIT + 2, persistent, chunk, blocks)
+    if persistent:
+        assert not g.check()
     for i, (c, p) in enumerate(zip(cases, plans)):
         iters, relres, status = p.finish()
         f0, u0, it0, rr0, st0 = solo[i]
@@ -156,3 +167,50 @@ def test_group_rejects_what_it_cannot_run():
     a.finish()
     b.finish()
     g.close()
+
+
+def test_persistent_group_fp32_mixed_grids_equal_solo():
+    """One persistent launch per iteration (abac_group_run): bitwise the solo solves."""
+    _check_members(FP32_MIX, "fp32", [700 + i for i in range(len(FP32_MIX))], persistent=True)
+
+
+def test_persistent_group_fp64_mixed_grids_equal_solo():
+    _check_members(FP64_MIX, "fp64", [800 + i for i in range(len(FP64_MIX))], persistent=True)
+
+
+def test_persistent_group_many_iterations_per_launch_with_late_members():
+    """Eight iterations per launch; two members join after two iterations of the others;
+    members that stop skip their work in the launches that follow."""
+    cases = [FP32_MIX[0], FP32_MIX[2], FP32_MIX[3], FP32_MIX[1]]
+    _check_members(cases, "fp32", [900, 901, 902, 903], late=(2, 3), persistent=True, chunk=8)
+
+
+@pytest.mark.parametrize("blocks", [1, 8, 40, 1024])
+def test_persistent_group_any_grid_size_equals_solo(blocks):
+    """Grids from one workgroup (every logical block in turn, no waiting at barriers) to
+    more than the largest step's blocks (capped): the same results."""
+    _check_members([FP64_MIX[1], FP64_MIX[2]], "fp64", [920, 921], persistent=True, chunk=4, blocks=blocks)
+
+
+def test_persistent_group_timeout_is_reported_and_recovered():
+    """A barrier wait limit of zero (forced from the host) makes the waiting blocks give
+    up at the first barrier: the launch ends, abac_group_check reports it, and the next
+    launch of the same group, with fresh members, again matches the solo solves."""
+    from paper_2306_03574_amd import Group
+    case = FP32_MIX[2]
+    g = Group(device=DEV)
+    p = _plan(case, "fp32")
+    _say(f"persistent timeout {case}")
+    p.begin(p.build_rhs(*_inputs(case[0], case[1], case[2], case[4], 11)), p.empty(), tol=TOL, maxit=MAXIT)
+    g.set([p])
+    g.run(1, timeout_s=1e-12)
+    torch.cuda.synchronize()
+    assert g.check()
+    assert not g.check()        # the flag was cleared
+    from paper_2306_03574_amd.abac import AbacError
+    try:
+        p.finish()              # the member's state is invalid; only its release is checked
+    except AbacError:
+        pass
+    g.close()
+    _check_members([FP32_MIX[0], FP32_MIX[3]], "fp32", [910, 911], persistent=True)
