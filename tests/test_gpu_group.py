@@ -185,6 +185,12 @@ def test_persistent_group_many_iterations_per_launch_with_late_members():
     _check_members(cases, "fp32", [900, 901, 902, 903], late=(2, 3), persistent=True, chunk=8)
 
 
+def test_persistent_group_1d_only_mix_equal_solo():
+    """1D members only: the y steps have no blocks and their barriers are skipped."""
+    cases = [(255, 0, 64, 1e-3, 1), (1023, 0, 64, 1e-2, 2), (2047, 0, 16, 1e-3, 1)]
+    _check_members(cases, "fp64", [930, 931, 932], persistent=True, chunk=3)
+
+
 @pytest.mark.parametrize("blocks", [1, 8, 40, 1024])
 def test_persistent_group_any_grid_size_equals_solo(blocks):
     """Grids from one workgroup (every logical block in turn, no waiting at barriers) to
