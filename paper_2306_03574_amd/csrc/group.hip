@@ -12,6 +12,9 @@
 // own kernels (one partial per logical matvec or vector block, one per mode pair of
 // the time pass), and each member keeps its own state, partials and snapshots.  A
 // member's results are therefore bitwise those of its solo solve.
+//
+// The persistent kernel runs the same step bodies for several iterations in one
+// cooperative launch, with a grid-wide barrier between steps (abac_group_run).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
