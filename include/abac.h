@@ -234,17 +234,19 @@ abac_status abac_group_set(abac_group *group, abac_plan *const *plans, int n);
 abac_status abac_group_advance(abac_group *group, int iterations);
 
 /* The same `iterations` MINRES iterations of every member as abac_group_advance, with
- * bitwise the same results, in ONE persistent launch: a cooperative launch of `blocks`
- * 256-thread workgroups (0: a default that balances barrier cost against parallelism;
- * always capped at what the device holds at once and at the largest step's logical
- * blocks), each taking every gridDim-th logical block of a step, with a grid-wide
- * barrier between steps.  Every block's barrier writes back and invalidates its XCD's
+ * bitwise the same results, in ONE persistent launch of `blocks` 256-thread workgroups
+ * (0: a default that balances barrier cost against parallelism; always capped at what
+ * the device holds at once and at the largest step's logical blocks), each taking
+ * every gridDim-th logical block of a step, with a grid-wide barrier between steps.
+ * Other work on the device can only delay the launch (its blocks become resident as
+ * that work ends).  Every block's barrier writes back and invalidates its XCD's
  * L2 (agent scope), so a barrier costs more per block than a launch costs per step:
  * the persistent launch suits groups of small grids run on few blocks.  A block that
  * waits longer than timeout_s seconds at a barrier (0: 2 s) leaves the launch, and so
  * do the others: the launch still ends, but the members' state is then invalid and
- * abac_group_check reports it.  Asynchronous as abac_group_advance; ABAC_EINVAL for
- * an argument out of range, ABAC_EDEVICE if the device refuses the launch. */
+ * abac_group_check reports it.  The device current at abac_group_create must be
+ * current.  Asynchronous as abac_group_advance; ABAC_EINVAL for an argument out of
+ * range or another current device, ABAC_EDEVICE if the device refuses the launch. */
 abac_status abac_group_run(abac_group *group, int iterations, int blocks, double timeout_s);
 
 /* Wait for the group's stream; *aborted = 1 if a persistent launch (abac_group_run)

@@ -392,8 +392,9 @@ class Group:
     def run(self, iterations: int = 1, blocks: int = 0, timeout_s: float = 0.0):
         """The same iterations as advance(), in one persistent launch of `blocks`
         workgroups (0: the library's default) (abac_group_run)."""
-        _check(self._lib.abac_group_run(self._h, int(iterations), int(blocks), float(timeout_s)),
-               "abac_group_run")
+        with torch.cuda.device(self.device):
+            _check(self._lib.abac_group_run(self._h, int(iterations), int(blocks), float(timeout_s)),
+                   "abac_group_run")
 
     def check(self) -> bool:
         """Whether a persistent launch gave up at a barrier since the last check."""

@@ -14,7 +14,7 @@
 // member's results are therefore bitwise those of its solo solve.
 //
 // The persistent kernel runs the same step bodies for several iterations in one
-// cooperative launch, with a grid-wide barrier between steps (abac_group_run).
+// launch, with a grid-wide barrier between steps (abac_group_run).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -356,7 +356,7 @@ __device__ __noinline__ void ps_time(const GroupTable* G, int w) { group_time<T>
 template <typename T>
 __device__ __noinline__ void ps_xinv(const GroupTable* G, int w) { group_xinv<T>(G, w); }
 
-// The grid is at most what the device holds at once (a cooperative launch); block k
+// The grid is at most what the device holds at once; block k
 // takes logical blocks k, k + gridDim.x, ... of each step, then the grid meets at a
 // barrier, so a step starts only once the step before has finished for every member,
 // as between the list kernels.  Each logical block runs the same body with the same
@@ -413,6 +413,7 @@ struct abac_group {
   hipEvent_t joined;             // members' set-up done (recorded on each member stream in turn)
   hipEvent_t done;               // the group's last enqueued work
   GridSync* d_sync;              // barrier state of the persistent kernel
+  int device;                    // the device current at creation (the group's memory lives there)
 };
 
 namespace {
@@ -550,9 +551,11 @@ abac_status abac_group_create(void* stream, abac_group** out) {
   }
   g->joined = g->done = nullptr;
   g->d_sync = nullptr;
+  g->device = 0;
   std::memset(g->blocks, 0, sizeof(g->blocks));
   std::memset(g->lds, 0, sizeof(g->lds));
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&g->d_table), sizeof(GroupTable));
+  hipError_t e = hipGetDevice(&g->device);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&g->d_table), sizeof(GroupTable));
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&g->d_sync), sizeof(GridSync));
   if (e == hipSuccess) e = hipMemsetAsync(g->d_sync, 0, sizeof(GridSync), g->stream);
   for (int k = 0; e == hipSuccess && k < kGroupStage; ++k) {
@@ -655,23 +658,29 @@ abac_status abac_group_run(abac_group* g, int iterations, int blocks, double tim
   if (!(timeout_s >= 0) || timeout_s > 3600) return gfail(ABAC_EINVAL, "timeout_s must be in [0, 3600]");
   if (blocks < 0) return gfail(ABAC_EINVAL, "blocks must be >= 0");
   if (iterations == 0 || g->members.empty()) return group_release(g);
-  const void* fn = g->prec == ABAC_PREC_FP32 ? reinterpret_cast<const void*>(&k_group_persistent<float>)
-                                             : reinterpret_cast<const void*>(&k_group_persistent<double>);
+  const bool fp32 = g->prec == ABAC_PREC_FP32;
+  const void* fn = fp32 ? reinterpret_cast<const void*>(&k_group_persistent<float>)
+                        : reinterpret_cast<const void*>(&k_group_persistent<double>);
   size_t lds = 0;
   int most = 0;
   for (int k = 0; k < GS_COUNT; ++k) {
     if (k != GS_FIN) lds = std::max(lds, g->lds[k]);
     most = std::max(most, g->blocks[k]);
   }
-  int dev = 0, ncu = 0, per_cu = 0, coop = 0, khz = 0;
-  GHIP(hipGetDevice(&dev));
-  GHIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
-  if (!coop) return gfail(ABAC_EDEVICE, "the device does not support cooperative launches");
+  const int dev = g->device;
+  int cur = 0, ncu = 0, per_cu = 0, khz = 0;
+  GHIP(hipGetDevice(&cur));
+  if (cur != dev) return gfail(ABAC_EINVAL, "the group's device must be current (the one at abac_group_create)");
   GHIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   GHIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
   GHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kGroupWG, lds));
   if (per_cu < 1) return gfail(ABAC_EINVAL, "the members' tiles leave no room for a persistent block");
-  // Every block must be resident at once.  A barrier costs each block its own L2
+  // Every block must be resident at once: the grid is capped at what the device holds
+  // (the occupancy of this kernel on every CU).  The launch is a plain one: a cooperative
+  // launch would also promise residency, but on this runtime it failed in a child process
+  // of a process that had made cooperative launches.  A block that other work keeps off the
+  // device only delays the barriers until that work ends; past the time limit the
+  // launch ends with the abort flag.  A barrier costs each block its own L2
   // write-back and invalidation, which the XCDs serve one block after another (about
   // 65 ns per block on MI355X), while fewer blocks take more logical blocks each (a few
   // microseconds per tile).  The default balances the two, sqrt(48 x the largest
@@ -684,10 +693,13 @@ abac_status abac_group_run(abac_group* g, int iterations, int blocks, double tim
       (unsigned long long)((timeout_s > 0 ? timeout_s : kGroupTimeout) * (double)khz * 1000.0);
   // a fresh barrier (count, gen, abort); the sticky flag stays for abac_group_check
   GHIP(hipMemsetAsync(g->d_sync, 0, offsetof(GridSync, aborted), g->stream));
-  GroupTable* table = g->d_table;
-  GridSync* sync = g->d_sync;
-  void* args[] = {&table, &iterations, &sync, &deadline};
-  GHIP(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kGroupWG), args, (unsigned)lds, g->stream));
+  if (fp32)
+    hipLaunchKernelGGL((k_group_persistent<float>), dim3(grid), dim3(kGroupWG), lds, g->stream, g->d_table, iterations,
+                       g->d_sync, deadline);
+  else
+    hipLaunchKernelGGL((k_group_persistent<double>), dim3(grid), dim3(kGroupWG), lds, g->stream, g->d_table,
+                       iterations, g->d_sync, deadline);
+  GHIP(hipGetLastError());
   GRUN(post_snapshots(g, iterations));
   return group_release(g);
 }
