@@ -10,7 +10,18 @@ mu^{-1/2} formed in single or double precision, and runs the oracle's MINRES wit
 each.  Measured: at alpha = 1e-2, 6 iterations in double precision, 10 with single-
 precision transforms and double-precision weights, 9 with both single, 8 with
 double-precision transforms and single-precision weights; at alpha = 1e-3, 6 and 8, 8, 8.
-The transforms' own rounding, not the weights, sets the count."""
+The transforms' own rounding, not the weights, sets the count.
+
+    python tests/fp32_rounding_study.py 1e-2 passes
+
+mirrors the GPU's passes instead, z = Sx Sy [K Y K Y] Sy Sx r with the scratch rounded
+to single precision between passes, and sets each pass's arithmetic (x DSTs, y DSTs,
+time FFTs) to single or double precision.  Measured at alpha = 1e-2 (the same counts in
+two runs): all double 8, all single 11, time pass double 8, x and y double 9, x double 9.
+An earlier draft of this emulation, differing only in where arrays were copied, gave
+9, 10 and 11 for the rows with a single-precision time pass: with single-precision
+time-pass arithmetic the count moves between 9 and 11 with the rounding details, and
+only double-precision time-pass arithmetic (8 in every variant) brings it within 2 of 6."""
 import os
 import sys
 import time
@@ -77,6 +88,48 @@ def make_pinv(fft32, w32):
         return z.astype(np.float64)
     return pinv
 
+def make_pass_pinv(x32, y32, t32):
+    """The GPU's pass structure with single-precision scratch between passes; each
+    pass's arithmetic in single (True) or double precision."""
+    M64 = pc.principal_inv_sqrt(pc.mu_table(g, alpha))
+    d64 = pc.time_scaling(nt, alpha)
+    M = M64.astype(np.complex64) if t32 else M64
+    ct = np.complex64 if t32 else np.complex128
+    rt = np.float32 if t32 else np.float64
+    d = d64.astype(rt)
+
+    def dst(v, axis, p32):
+        return sfft.dst(np.asarray(v, dtype=np.float32 if p32 else np.float64), type=1, axis=axis, norm="ortho",
+                        workers=-1)
+
+    def K(v):
+        v = (v * d[:, None, None]).astype(ct)
+        v = sfft.ifft((M * sfft.fft(v, axis=0, workers=-1)).astype(ct), axis=0, workers=-1)
+        return (v.real.astype(rt) / d[:, None, None]).astype(rt)
+
+    def pinv(r):
+        v = dst(r, 2, x32).astype(np.float32)
+        v = dst(v, 1, y32).astype(np.float32)
+        w = K(K(v.astype(rt)[::-1])[::-1]).astype(np.float32)
+        w = dst(w, 1, y32).astype(np.float32)
+        return np.asarray(dst(w, 2, x32), dtype=np.float64)
+    return pinv
+
+
+def main_passes():
+    src, p0, p1, _ = synth.manufactured_2d(nx, ny, nt)
+    f = aao.build_rhs(g, src, p0, p1)
+    L = L_matrix(g)
+    for name, x32, y32, t32 in [("all double", False, False, False), ("all single", True, True, True),
+                                ("time double", True, True, False), ("x, y double", False, False, True),
+                                ("x double", False, True, True)]:
+        P = make_pass_pinv(x32, y32, t32)
+        t0 = time.time()
+        r = mr.minres(lambda v: aao.apply_A(g, v, L), P, aao.reverse_time(f), tol=1e-8, maxit=60)
+        print(f"alpha {alpha}: passes, {name:14s} iters {r.iters} converged {r.converged} ({time.time() - t0:.0f} s)",
+              flush=True)
+
+
 def main():
     src, p0, p1, _ = synth.manufactured_2d(nx, ny, nt)
     f = aao.build_rhs(g, src, p0, p1)
@@ -91,4 +144,4 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    main_passes() if len(sys.argv) > 2 and sys.argv[2] == "passes" else main()
