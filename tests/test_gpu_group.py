@@ -220,3 +220,40 @@ def test_persistent_group_timeout_is_reported_and_recovered():
         pass
     g.close()
     _check_members([FP32_MIX[0], FP32_MIX[3]], "fp32", [910, 911], persistent=True)
+
+
+def test_persistent_group_random_mixes_equal_list_launches():
+    """Twelve seeded random mixes (1 to 4 members, FP32 or FP64), grid sizes and iteration
+    counts: the persistent launch gives bitwise the iterates of one launch per step."""
+    import random
+    from paper_2306_03574_amd import Group
+    pool = [(255, 0, 64, 1e-3, 1), (1023, 0, 64, 1e-2, 2), (63, 63, 64, 1e-3, 1), (31, 15, 32, 1e-3, 1),
+            (127, 63, 32, 1e-3, 2), (2047, 0, 16, 1e-3, 1), (127, 127, 128, 1e-2, 1), (63, 63, 256, 1e-2, 1)]
+    rng = random.Random(2024)
+    for trial in range(12):
+        prec = rng.choice(["fp32", "fp64"])
+        cases = rng.sample(pool, rng.randint(1, 4))
+        blocks = rng.choice([0, 1, 8, 40, 128, 1024])
+        iters = rng.randint(1, 5)
+        _say(f"random trial {trial}: {prec} blocks {blocks} iterations {iters} {cases}")
+        out = {}
+        for mode in ("advance", "run"):
+            plans, us = [], []
+            for i, c in enumerate(cases):
+                p = _plan(c, prec)
+                p.begin(p.build_rhs(*_inputs(c[0], c[1], c[2], c[4], 1000 + 10 * trial + i)), u := p.empty(),
+                        tol=1e-30, maxit=1000)
+                plans.append(p)
+                us.append(u)
+            g = Group(device=DEV)
+            g.set(plans)
+            if mode == "advance":
+                g.advance(iters)
+            else:
+                g.run(iters, blocks=blocks)
+                assert not g.check()
+            out[mode] = [(p.finish(), _host(u)) for p, u in zip(plans, us)]
+            g.close()
+        for (ra, ua), (rb, ub) in zip(out["advance"], out["run"]):
+            assert ra == rb, (trial, ra, rb)
+            assert np.array_equal(ua, ub), (trial, float(np.max(np.abs(ua - ub))))
